@@ -1,0 +1,32 @@
+"""Workload definitions: grid sizes, macro step H, number of macro steps.
+
+H follows the rule "a fixed fraction of the stability limit":
+H = frac * ISB / rho with rho = c_max * sigma * sqrt(d) / dx the spectral
+radius of the centred-difference operator (sigma = max over theta of the
+1-D symbol s(theta)).  The two constants below are rounded in the safe
+direction; a test recomputes both with the oracle.
+"""
+import math
+
+from . import schemes
+
+ISB_ORDER8_K6 = 8.0165        # imaginary stability boundary of ORDER8_K6 (exact 8.016569...)
+ISB_SQUARE4 = 3.3635          # of SQUARE4_2_4 (exact 3.36358...)
+SIGMA_FD4 = 1.3722221         # max of (8 sin t - sin 2t)/6      (exact 1.37222201...)
+SIGMA_FD8 = 1.7305985         # same for the 8th-order stencil  (exact 1.73059838...)
+
+
+def stable_H(isb, c_max, dx, d, sigma, frac=0.8):
+    return frac * isb * dx / (c_max * sigma * math.sqrt(d))
+
+
+# 1-D advection, M = 256, FD4, square order 4, t = 1 in 131 macro steps
+# (131 is the smallest count with H = 1/n below 0.8 of the limit).
+CONFIG_ADVECTION1D = dict(name="advection1d_m256_square4", m=256, r=2,
+                          scheme=schemes.SQUARE4_2_4, H=1.0 / 131, n_macro=131)
+
+# 2-D acoustic, 2048^2, constant c = 1, FD4, order 8 over {2..12}, 500 macro steps.
+CONFIG_ACOUSTIC2D = dict(name="acoustic2d_2048_fd4_order8_k6", n=2048, r=2, c2=1.0,
+                         scheme=schemes.ORDER8_K6,
+                         H=stable_H(ISB_ORDER8_K6, 1.0, 1.0 / 2048, 2, SIGMA_FD4),
+                         n_macro=500)
