@@ -1,0 +1,191 @@
+/*
+ * gbs.h — C ABI of the MI355X (gfx950) extrapolated Gragg–Bulirsch–Stoer
+ * time stepper for method-of-lines wave problems.
+ *
+ * Method (Ellison & Fornberg, "A parallel-in-time approach for wave-type
+ * PDEs"): for y' = f(t, y) and a macro step H, each of k sequences with an
+ * even step count N_j and substep h_j = H / N_j runs
+ *     y_1 = y_0 + h f(t_0, y_0)                        forward Euler
+ *     y_{n+1} = y_{n-1} + 2 h f(t_0 + n h, y_n)        leap-frog, n = 1..N_j
+ *     y*_j = (y_{N-1} + 2 y_N + y_{N+1}) / 4           averaging
+ * (Sect. 2.1, eq. GBS) and the step returns y_out = sum_j c_j y*_j
+ * (Sect. 3.2) with weights c that satisfy the order constraints of eq.
+ * (vander) and, when k > p/2, free weights chosen for the stability domain
+ * (Sect. 3.7, eqs. order_constraints and cdep_computation).  f(t_0, y_0) is
+ * the same for every sequence and is evaluated once (Sect. 3.6).
+ *
+ * Conventions for every entry point:
+ *  - Return value: GBS_OK (0) or a negative status; gbs_last_error() then
+ *    returns a message for the calling thread.  No C++ exception crosses the
+ *    ABI.
+ *  - "host" pointers are read during the call only (copied where kept);
+ *    "device" pointers are HIP device memory owned by the caller.  The
+ *    library allocates no device memory: every scratch buffer lives in the
+ *    caller's workspace.
+ *  - Device work is enqueued on the plan's HIP stream and the call returns
+ *    without synchronising; a fault in device code surfaces at the caller's
+ *    next synchronisation.
+ *  - A plan is not thread-safe; calls on one plan must not overlap.
+ *
+ * Data layout: a state is a contiguous array [R][F][Z][Y][X] (x fastest) of
+ * the plan's dtype, R independent right-hand sides, F fields:
+ *   GBS_ADVECT1D    F = 1 (u),                          grid X
+ *   GBS_ACOUSTIC2D  F = 3 (p, v_x, v_y),                grid Y x X
+ *   GBS_ACOUSTIC3D  F = 4 (p, v_x, v_y, v_z),           grid Z x Y x X
+ * on the periodic unit box with spacing 1/n per axis.  The operators are the
+ * periodic centred first-derivative stencils of order 4 or 8:
+ *   advection  u_t = -u_x
+ *   acoustic   p_t = -c^2 div v + sum_s w_s r(t) delta_s,   v_t = -grad p
+ * with r the Ricker wavelet of the plan's sources (if any).
+ */
+#ifndef GBS_H
+#define GBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GBS_OK = 0,
+  GBS_EINVAL = -1,      /* null pointer, bad size, shape or enum value          */
+  GBS_ESTEPS = -2,      /* step count odd, non-positive, duplicated; k < p/2    */
+  GBS_EORDER = -3,      /* order p odd or <= 0; p = 2 (mod 4) for a wave plan   */
+  GBS_ESINGULAR = -4,   /* order-constraint system singular                      */
+  GBS_EUNSTABLE = -5,   /* H exceeds ISB(R) / spectral radius of the operator    */
+  GBS_EDEVICE = -6,     /* a HIP call failed                                     */
+  GBS_ENOMEM = -7,      /* workspace too small                                   */
+  GBS_EUNSUPPORTED = -8 /* combination not built (operator, order, dtype)        */
+};
+
+enum { GBS_ADVECT1D = 1, GBS_ACOUSTIC2D = 2, GBS_ACOUSTIC3D = 3 };
+enum { GBS_F32 = 1, GBS_F64 = 2 };
+/* plan flags */
+enum { GBS_FLAG_NO_STABILITY_CHECK = 1 };
+
+typedef struct gbs_problem {
+  int32_t op;           /* GBS_ADVECT1D / GBS_ACOUSTIC2D / GBS_ACOUSTIC3D            */
+  int32_t fd_order;     /* 4 or 8                                                    */
+  int64_t n[3];         /* points along x, y, z (unused axes: 1)                     */
+  int32_t n_rhs;        /* R >= 1 independent states sharing the coefficient field   */
+  int32_t dtype;        /* GBS_F64, or GBS_F32 (stepping in FP32; the averaging and  */
+                        /* the weighted combination are always accumulated in FP64)  */
+  double c2;            /* constant c^2 (acoustic) when c2_field is NULL             */
+  const void* c2_field; /* device, [Z][Y][X] in dtype, or NULL                       */
+  double c_max;         /* max |c| over the grid; required with c2_field (stability) */
+  int32_t flags;        /* GBS_FLAG_*                                                */
+  int32_t reserved;
+} gbs_problem;
+
+typedef struct gbs_scheme {
+  int32_t p;              /* order of the extrapolated step (even)            */
+  int32_t k;              /* number of sequences, 1 <= k <= GBS_MAX_SEQ        */
+  const int32_t* steps;   /* host [k]: even, distinct step counts N_j          */
+  const double* weights;  /* host [k]: c_j, usually from gbs_weights()         */
+} gbs_scheme;
+
+#define GBS_MAX_SEQ 16
+#define GBS_MAX_SRC 16
+
+typedef struct gbs_plan gbs_plan;
+
+/*
+ * gbs_weights — order-constraint weights (Sect. 3.2 eq. vander; Sect. 3.7
+ * eqs. order_constraints and cdep_computation).
+ *   p         order (even, > 0); the system has p/2 rows k = 0..p/2-1 with
+ *             entries n_i^(-2k) (the H^(2k) row scale cancels) and b = e_1.
+ *   m         number of step counts; m >= p/2.
+ *   steps     host [m] step counts (even, distinct, > 0).
+ *   n_free    m - p/2 (or 0 when m = p/2).
+ *   free_idx  host [n_free] positions in steps of the free weights, or NULL.
+ *   c_free_num, c_free_den  host [n_free] the free weights as exact
+ *             fractions num/den (den > 0), or NULL when n_free = 0.
+ *   c_out     host [m] out: every weight rounded to the nearest double (ties
+ *             to even) after an exact rational solve for the dependent ones.
+ *   isb_out   host out, nullable: imaginary stability boundary of the exact
+ *             R(xi) = sum c_i P_i(xi) (App. A/B), found from the exact
+ *             polynomial |R(iy)|^2 - 1 with its zero at the origin divided
+ *             out (0 when |R| > 1 next to the origin, e.g. p = 2 mod 4).
+ * Host-only: needs no GPU.
+ */
+int gbs_weights(int32_t p, int32_t m, const int32_t* steps, int32_t n_free,
+                const int32_t* free_idx, const int64_t* c_free_num,
+                const int64_t* c_free_den, double* c_out, double* isb_out);
+
+/*
+ * gbs_isb — imaginary stability boundary of sum_j c_j P_{N_j} for the given
+ * FP64 weights taken at their exact binary values (App. A; Sect. 2.2).
+ * Host-only.
+ */
+int gbs_isb(int32_t k, const int32_t* steps, const double* weights, double* isb_out);
+
+/*
+ * gbs_plan_workspace_bytes — device workspace needed by a plan: one FP64
+ * accumulator state plus two levels per sequence in the plan's dtype,
+ * each 256-byte aligned.
+ */
+int gbs_plan_workspace_bytes(const gbs_problem* prob, const gbs_scheme* sch, size_t* bytes);
+
+/*
+ * gbs_plan_create — validate and build a plan.
+ *   prob, sch  host, copied.
+ *   H          macro step (> 0).  Unless GBS_FLAG_NO_STABILITY_CHECK is set,
+ *              H * rho must not exceed the ISB of the scheme, with rho =
+ *              c_max * sigma * sqrt(sum_axes n_a^2), sigma = max_theta of the
+ *              stencil's symbol (App. A: the operator's eigenvalues must lie
+ *              in the stability domain) -> GBS_EUNSTABLE.
+ *   workspace  device, at least gbs_plan_workspace_bytes(); owned by the
+ *              caller, must outlive the plan, and must not be shared by
+ *              plans whose calls overlap.
+ *   hip_stream hipStream_t to enqueue on (NULL: the null stream).
+ */
+int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gbs_scheme* sch,
+                    double H, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/*
+ * gbs_plan_set_sources — point sources on the pressure equation of an
+ * acoustic plan: f_p[rhs[s]][flat_index[s]] += weight[s] * r(t), with the
+ * Ricker wavelet r(t) = (1 - 2 a) exp(-a), a = (pi f0 (t - delay))^2,
+ * evaluated on the host in FP64 at every substep time t_0 + n h_j.
+ *   n_src <= GBS_MAX_SRC (0 removes the sources); arrays host [n_src];
+ *   flat_index is the index within one field ([Z][Y][X], x fastest).
+ */
+int gbs_plan_set_sources(gbs_plan* plan, int32_t n_src, const int32_t* rhs,
+                         const int64_t* flat_index, const double* weight, double f0,
+                         double delay);
+
+/*
+ * gbs_step — n_macro extrapolated macro steps starting at time t0
+ * (macro step i starts at t0 + i*H).
+ *   y_in   device state at t0.
+ *   y_out  device state at t0 + n_macro*H; may alias y_in.
+ */
+int gbs_step(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void* y_out);
+
+/*
+ * gbs_plan_set_timing — enabled != 0: every kernel launch is bracketed by HIP
+ * events on the plan's stream, and gbs_plan_get_timing() returns the summed
+ * duration (ms) and the launch count of the leap-frog kernel and of the
+ * first-evaluation kernel since the last reset (the read synchronises the
+ * stream and resets).  enabled > 1 also creates the events for that many
+ * macro steps up front.  enabled = 0 turns timing off.
+ */
+int gbs_plan_set_timing(gbs_plan* plan, int32_t enabled);
+int gbs_plan_get_timing(gbs_plan* plan, double* lf_ms, int64_t* lf_launches,
+                        double* first_ms, int64_t* first_launches);
+
+/* Updates (grid point x RHS x f-evaluation) one macro step performs. */
+int gbs_plan_updates_per_macro_step(const gbs_plan* plan, double* updates);
+
+int gbs_plan_destroy(gbs_plan* plan);
+
+/* Message for the last non-zero status returned on this thread. */
+const char* gbs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBS_H */

@@ -1,0 +1,110 @@
+// Device-side building blocks: periodic centred first-derivative stencils
+// of order 4 and 8, and the per-launch argument blocks of the step kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/gbs.h"
+
+namespace gbs {
+
+// D u_i = (1/dx) sum_{k=1..R} a_k (u_{i+k} - u_{i-k}); the a_k are written
+// as integers W_k over a common denominator DEN, so that
+// D u_i = inv * sum_k W_k (u_{i+k} - u_{i-k}) with inv = n / DEN.
+template <int ORDER>
+struct Fd;
+template <>
+struct Fd<4> {
+  static constexpr int R = 2;
+  static constexpr double DEN = 12.0;
+  template <typename T>
+  __device__ static T w(int k) { return k == 0 ? T(8) : T(-1); }
+};
+template <>
+struct Fd<8> {
+  static constexpr int R = 4;
+  static constexpr double DEN = 840.0;
+  template <typename T>
+  __device__ static T w(int k) {
+    return k == 0 ? T(672) : (k == 1 ? T(-168) : (k == 2 ? T(32) : T(-3)));
+  }
+};
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Sum_k W_k (u[i+k] - u[i-k]) along an axis with stride `stride` and
+// periodic length n, around the index `i` (0 <= i < n); `base` points at
+// element 0 of that line.
+template <typename T, int ORDER>
+__device__ __forceinline__ T dsum(const T* __restrict__ base, int i, int n, int64_t stride) {
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < Fd<ORDER>::R; ++k) {
+    const T up = base[(int64_t)wrap(i + k + 1, n) * stride];
+    const T dn = base[(int64_t)wrap(i - k - 1, n) * stride];
+    s += Fd<ORDER>::template w<T>(k) * (up - dn);
+  }
+  return s;
+}
+
+// Mode bits of one sequence in one leap-frog launch.
+enum : int32_t {
+  MODE_LAST = 1,    // s == N_j: average, combine, no level written
+  MODE_FIRST = 2,   // first sequence to finish: acc = c y*
+  MODE_FINAL = 4,   // last sequence to finish: y_out = acc + c y*
+};
+
+template <typename T>
+struct SeqDesc {
+  const T* cur;    // y_s
+  const T* old;    // y_{s-1}
+  T* out;          // y_{s+1} (overwrites old's buffer), unused when MODE_LAST
+  T h2;            // 2 h_j
+  int32_t mode;
+  double cw;       // c_j
+  double amp;      // source wavelet at t_0 + s h_j
+};
+
+struct SrcDesc {
+  int64_t idx;     // within one field
+  double w;
+  int32_t rhs;
+  int32_t pad;
+};
+
+struct Geometry {
+  int32_t nx, ny, nz;
+  int32_t nsrc;
+  int64_t field;   // points per field
+  int64_t state;   // elements per right-hand side (F * field)
+};
+
+template <typename T>
+struct StepArgs {
+  SeqDesc<T> seq[GBS_MAX_SEQ];
+  SrcDesc src[GBS_MAX_SRC];
+  Geometry g;
+  double* acc;     // FP64 accumulator, state-sized
+  T* yout;
+  const T* c2f;    // coefficient field or null
+  T c2c;           // constant coefficient
+  T invx, invy, invz;
+};
+
+template <typename T>
+struct FirstArgs {
+  T* out[GBS_MAX_SEQ];   // y_1 of every sequence
+  T h[GBS_MAX_SEQ];
+  SrcDesc src[GBS_MAX_SRC];
+  Geometry g;
+  const T* y0;
+  const T* c2f;
+  T c2c;
+  T invx, invy, invz;
+  int32_t nseq;
+  double amp;            // source wavelet at t_0
+};
+
+}  // namespace gbs

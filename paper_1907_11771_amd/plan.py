@@ -1,0 +1,108 @@
+"""A torch-facing wrapper of one library plan: device memory (workspace,
+coefficient field) comes from torch, kernels are enqueued on torch's current
+HIP stream.  No arithmetic of the method happens here."""
+import ctypes
+
+import torch
+
+from . import binding as B
+
+_DT = {torch.float64: B.F64, torch.float32: B.F32}
+_FIELDS = {B.ADVECT1D: 1, B.ACOUSTIC2D: 3, B.ACOUSTIC3D: 4}
+
+
+def scheme_weights(scheme):
+    """(steps, FP64 weights, ISB) of a scheme spec {p, steps, free_idx, c_free}
+    with c_free given as "num/den" strings."""
+    pairs = []
+    for s in scheme["c_free"]:
+        num, den = str(s).split("/")
+        pairs.append((int(num), int(den)))
+    w, isb = B.weights(scheme["p"], scheme["steps"], scheme["free_idx"], pairs)
+    return list(scheme["steps"]), w, isb
+
+
+class GBSPlan:
+    """op: B.ADVECT1D / B.ACOUSTIC2D / B.ACOUSTIC3D; n: grid sizes (x[, y[, z]])."""
+
+    def __init__(self, op, n, p, steps, w, H, fd_order=4, n_rhs=1, dtype=torch.float64,
+                 c2=1.0, c2_field=None, c_max=None, device="cuda", check_stability=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("GBSPlan needs a HIP device; there is no CPU path")
+        self.device = torch.device(device)
+        self.dtype = dtype
+        self.op, self.n, self.n_rhs = op, tuple(int(x) for x in n), n_rhs
+        self.H = float(H)
+        self.steps, self.w, self.p = list(steps), list(w), p
+        flags = 0 if check_stability else B.FLAG_NO_STABILITY_CHECK
+        self.c2_field = None
+        ptr = None
+        if c2_field is not None:
+            self.c2_field = c2_field.to(device=self.device, dtype=dtype).contiguous()
+            ptr = self.c2_field.data_ptr()
+            if c_max is None:
+                c_max = float(self.c2_field.max().sqrt())
+        self.problem = B.make_problem(op, self.n, fd_order, n_rhs, _DT[dtype], c2, ptr,
+                                      c_max or 0.0, flags)
+        self.scheme = B.make_scheme(p, steps, w)
+        nbytes = B.workspace_bytes(self.problem, self.scheme)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.handle = B.plan_create(self.problem, self.scheme, self.H, self.workspace.data_ptr(),
+                                    self.workspace.numel(), self.stream.cuda_stream)
+
+    @property
+    def state_shape(self):
+        return (self.n_rhs, _FIELDS[self.op]) + tuple(reversed(self.n))
+
+    def _check_state(self, t):
+        if t.device != self.device or t.dtype != self.dtype or not t.is_contiguous():
+            raise ValueError("state must be a contiguous %s tensor on %s" % (self.dtype, self.device))
+        if t.numel() != int(torch.Size(self.state_shape).numel()):
+            raise ValueError("state must have %s elements laid out as %s"
+                             % (torch.Size(self.state_shape).numel(), self.state_shape))
+
+    def step(self, y, out=None, t0=0.0, n_macro=1):
+        """n_macro macro steps from time t0; returns the output tensor (``out``
+        may be ``y`` itself)."""
+        self._check_state(y)
+        if out is None:
+            out = torch.empty_like(y)
+        self._check_state(out)
+        B.check(B.lib().gbs_step(self.handle, float(t0), int(n_macro), y.data_ptr(),
+                                 out.data_ptr()))
+        return out
+
+    def set_sources(self, rhs, flat_index, weight, f0, delay):
+        n = len(rhs)
+        B.check(B.lib().gbs_plan_set_sources(self.handle, n, B._arr(ctypes.c_int32, rhs),
+                                             B._arr(ctypes.c_int64, flat_index),
+                                             B._arr(ctypes.c_double, weight), float(f0),
+                                             float(delay)))
+
+    def set_timing(self, on):
+        """on: bool, or the number of macro steps to create events for."""
+        B.check(B.lib().gbs_plan_set_timing(self.handle, int(on)))
+
+    def get_timing(self):
+        """(leap-frog ms, launches, first-evaluation ms, launches) since the
+        last read."""
+        a, b = ctypes.c_double(), ctypes.c_int64()
+        c, d = ctypes.c_double(), ctypes.c_int64()
+        B.check(B.lib().gbs_plan_get_timing(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                            ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def updates_per_macro_step(self):
+        out = ctypes.c_double()
+        B.check(B.lib().gbs_plan_updates_per_macro_step(self.handle, ctypes.byref(out)))
+        return out.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                B.lib().gbs_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None

@@ -1,0 +1,149 @@
+"""GPU parity: the HIP library against the CPU oracle on identical seeded
+inputs.  FP64 bar: max |gpu - oracle| / max |oracle| <= 1e-12 per field."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gbs as G
+from oracle import operators as OP
+from oracle import spectral as SP
+from paper_1907_11771_amd import binding as B
+from synth import fields, schemes, workloads
+from tests.gpu_util import lib_plan, oracle_weights, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+def test_weights_used_by_plan_are_the_oracles():
+    for sch in (schemes.SQUARE4_2_4, schemes.ORDER8_K6):
+        plan = lib_plan(B.ADVECT1D, (64,), sch, 1e-4)
+        assert plan.w == oracle_weights(sch)[1]
+
+
+def test_advection1d_config_vs_oracle_and_closed_form():
+    cfg = workloads.CONFIG_ADVECTION1D
+    steps, c = oracle_weights(cfg["scheme"])
+    u0 = fields.advection_modes(cfg["m"])
+    plan = lib_plan(B.ADVECT1D, (cfg["m"],), cfg["scheme"], cfg["H"])
+    y = to_dev(u0.reshape(1, 1, -1))
+    out = plan.step(y, n_macro=cfg["n_macro"])
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(1, -1)
+    direct = G.integrate(OP.Advection1D(cfg["m"]), 0.0, u0, cfg["H"], cfg["n_macro"], steps, c)
+    closed = SP.advection1d(u0, cfg["H"], steps, c, cfg["n_macro"])
+    assert rel_err(got, direct) <= TOL64
+    assert rel_err(got, closed) <= TOL64
+
+
+@pytest.mark.parametrize("shape,order", [((72, 100), 4), ((40, 56), 8), ((33, 17), 4)])
+def test_acoustic2d_constant_c_vs_oracle(shape, order):
+    ny, nx = shape
+    sch = schemes.ORDER8_K6
+    steps, c = oracle_weights(sch)
+    sig = workloads.SIGMA_FD4 if order == 4 else workloads.SIGMA_FD8
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, 1.0, 1.0 / max(nx, ny), 2, sig)
+    rng = np.random.default_rng(7)
+    y0 = rng.standard_normal((3, ny, nx))
+    plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, fd_order=order, check_stability=False)
+    out = plan.step(to_dev(y0[None]), n_macro=4)
+    got = out.cpu().numpy()[0]
+    want = G.integrate(OP.Acoustic((ny, nx), c2=1.0, r=order // 2), 0.0, y0, H, 4, steps, c)
+    for q in range(3):
+        assert rel_err(got[q], want[q]) <= TOL64, q
+
+
+def test_acoustic2d_variable_c2_with_source_vs_oracle():
+    n = 96
+    sch = schemes.ORDER8_K6
+    steps, c = oracle_weights(sch)
+    cs = fields.lognormal_speed((n, n), seed=21)
+    c2 = cs ** 2
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / n, 2, workloads.SIGMA_FD4)
+    s = fields.ricker_source_2d(n, cells_per_wavelength=8.0)
+    y0 = fields.acoustic2d_pulse_modes(n, n_modes=6, kmax=4, width=0.05, seed=3)
+    plan = lib_plan(B.ACOUSTIC2D, (n, n), sch, H, c2_field=to_dev(c2), c_max=float(cs.max()))
+    flat = s["idx"][0] * n + s["idx"][1]
+    plan.set_sources([0], [flat], [s["weight"]], s["f0"], s["delay"])
+    n_macro = 6
+    t0 = 0.25 * s["delay"]
+    out = plan.step(to_dev(y0[None]), t0=t0, n_macro=n_macro)
+    got = out.cpu().numpy()[0]
+    op = OP.Acoustic((n, n), c2=c2, r=2,
+                     sources=[OP.Source(s["idx"], s["f0"], s["delay"], s["weight"])])
+    want = G.integrate(op, t0, y0, H, n_macro, steps, c)
+    for q in range(3):
+        assert rel_err(got[q], want[q]) <= TOL64, q
+
+
+def test_acoustic3d_fd8_variable_c2_multi_rhs_vs_oracle():
+    shape = (12, 20, 24)   # z, y, x
+    sch = schemes.ORDER8_K6
+    steps, c = oracle_weights(sch)
+    cs = fields.lognormal_speed(shape, seed=5)
+    c2 = cs ** 2
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / 24, 3, workloads.SIGMA_FD8)
+    rng = np.random.default_rng(9)
+    y0 = rng.standard_normal((2, 4) + shape)
+    plan = lib_plan(B.ACOUSTIC3D, (24, 20, 12), sch, H, fd_order=8, n_rhs=2,
+                    c2_field=to_dev(c2), c_max=float(cs.max()))
+    srcs = [(0, (6, 10, 12)), (1, (3, 4, 5))]
+    flat = [z * 20 * 24 + y * 24 + x for _, (z, y, x) in srcs]
+    f0, delay = 30.0, 0.05
+    plan.set_sources([0, 1], flat, [50.0, -20.0], f0, delay)
+    out = plan.step(to_dev(y0), n_macro=3)
+    got = out.cpu().numpy()
+    for r, (w_, (idx)) in enumerate(zip([50.0, -20.0], [srcs[0][1], srcs[1][1]])):
+        op = OP.Acoustic(shape, c2=c2, r=4, sources=[OP.Source(idx, f0, delay, w_)])
+        want = G.integrate(op, 0.0, y0[r], H, 3, steps, c)
+        for q in range(4):
+            assert rel_err(got[r, q], want[q]) <= TOL64, (r, q)
+
+
+def test_in_place_and_repeatable():
+    n = 64
+    sch = schemes.ORDER8_K6
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, 1.0, 1.0 / n, 2, workloads.SIGMA_FD4)
+    y0 = to_dev(np.random.default_rng(1).standard_normal((1, 3, n, n)))
+    plan = lib_plan(B.ACOUSTIC2D, (n, n), sch, H)
+    a = plan.step(y0, n_macro=5)
+    b = plan.step(y0, n_macro=5)
+    c = y0.clone()
+    plan.step(c, out=c, n_macro=5)
+    assert torch.equal(a, b) and torch.equal(a, c)
+    z = plan.step(y0, n_macro=0)
+    assert torch.equal(z, y0)
+
+
+def test_fp32_stepping_error_vs_fp64():
+    # FP32 levels, FP64 averaging and combination.  Stated bound for 20
+    # macro steps on a 128^2 grid: max rel error <= 2e-5 (measured ~ 2-5e-6;
+    # the scale is u32 * sum|c| * sqrt(number of rounding steps)).
+    n = 128
+    sch = schemes.ORDER8_K6
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, 1.0, 1.0 / n, 2, workloads.SIGMA_FD4)
+    y0 = fields.acoustic2d_pulse_modes(n, n_modes=8, kmax=6, width=0.05, seed=4)
+    p64 = lib_plan(B.ACOUSTIC2D, (n, n), sch, H)
+    p32 = lib_plan(B.ACOUSTIC2D, (n, n), sch, H, dtype=torch.float32)
+    a = p64.step(to_dev(y0[None]), n_macro=20).cpu().numpy()
+    b = p32.step(to_dev(y0[None], torch.float32), n_macro=20).cpu().numpy()
+    err = rel_err(b, a)
+    print("fp32 vs fp64 rel err", err)
+    assert err <= 2e-5
+
+
+def test_acoustic2d_full_size_500_steps_vs_closed_form():
+    # the benchmark's workload at full size and length, in the same launch
+    # configuration; the constant-c closed form gives every grid value
+    cfg = workloads.CONFIG_ACOUSTIC2D
+    n = cfg["n"]
+    steps, c = oracle_weights(cfg["scheme"])
+    y0 = fields.acoustic2d_pulse_modes(n)
+    plan = lib_plan(B.ACOUSTIC2D, (n, n), cfg["scheme"], cfg["H"])
+    out = plan.step(to_dev(y0[None]), n_macro=cfg["n_macro"])
+    got = out.cpu().numpy()[0]
+    want = SP.acoustic(y0, 1.0, cfg["H"], steps, c, cfg["n_macro"])
+    errs = [rel_err(got[q], want[q]) if q == 0 else
+            float(np.max(np.abs(got[q] - want[q])) / np.max(np.abs(want[0]))) for q in range(3)]
+    print("full-size rel errors", errs)
+    assert max(errs) <= TOL64

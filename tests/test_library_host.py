@@ -1,0 +1,136 @@
+"""CPU-side checks of the C-ABI library: it loads, exports what the header
+declares, and its host-only logic (exact weights, ISB, plan validation)
+agrees with the oracle.  No kernel is launched."""
+import ctypes
+from fractions import Fraction
+
+import pytest
+
+from oracle import stability as S
+from oracle import weights as W
+from paper_1907_11771_amd import binding as B
+from synth import schemes, workloads
+
+
+def test_library_exports_every_header_symbol():
+    L = B.lib()
+    names = B.header_symbols()
+    assert "gbs_step" in names and "gbs_weights" in names and len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("sch", schemes.ALL, ids=lambda s: s["name"])
+def test_weights_match_oracle_exactly(sch):
+    pairs = [tuple(int(v) for v in x.split("/")) for x in sch["c_free"]]
+    w, isb = B.weights(sch["p"], sch["steps"], sch["free_idx"], pairs)
+    exact = W.weights(sch["p"], sch["steps"], sch["free_idx"], [Fraction(x) for x in sch["c_free"]])
+    assert w == W.to_fp64(exact)                     # bit-identical nearest doubles
+    want = S.isb(S.extrapolated_poly(sch["steps"], exact))
+    # located in long double with a rounding-bound threshold: ~1e-7 relative
+    assert isb == pytest.approx(want, rel=1e-6, abs=1e-12)
+
+
+def test_isb_of_fp64_weights_and_zero_case():
+    # order 6: no coverage for the exact weights; rounding the weights to
+    # FP64 leaves an O(eps) low-order term, so the rounded polynomial covers
+    # at most a sliver of the axis
+    assert B.weights(6, [2, 4, 6])[1] == 0.0
+    w = W.to_fp64(W.weights(6, [2, 4, 6]))
+    assert B.isb([2, 4, 6], w) < 0.2
+    w = W.to_fp64(W.weights(4, [2, 4]))
+    assert B.isb([2, 4], w) == pytest.approx(3.3635857, abs=1e-6)
+
+
+@pytest.mark.parametrize("steps,err", [([2, 3], B.GBS_ESTEPS), ([2, 2], B.GBS_ESTEPS),
+                                       ([0, 2], B.GBS_ESTEPS)])
+def test_weights_reject_bad_steps(steps, err):
+    with pytest.raises(B.GBSError) as e:
+        B.weights(4, steps)
+    assert e.value.status == err
+
+
+def test_weights_reject_bad_order():
+    with pytest.raises(B.GBSError) as e:
+        B.weights(5, [2, 4, 6])
+    assert e.value.status == B.GBS_EORDER
+    with pytest.raises(B.GBSError) as e:
+        B.weights(8, [2, 4, 6])                          # k < p/2
+    assert e.value.status == B.GBS_ESTEPS
+
+
+# plan validation runs entirely on the host: a dummy (never dereferenced)
+# workspace address stands in for device memory, and no step is taken.
+FAKE_WS = 1 << 20
+
+
+def _plan(op, n, p, steps, w, H, **kw):
+    pr = B.make_problem(op, n, **kw)
+    sc = B.make_scheme(p, steps, w)
+    nb = B.workspace_bytes(pr, sc)
+    h = B.plan_create(pr, sc, H, FAKE_WS, nb)
+    B.plan_destroy(h)
+    return nb
+
+
+def _cfg2():
+    sch = schemes.ORDER8_K6
+    pairs = [tuple(int(v) for v in x.split("/")) for x in sch["c_free"]]
+    w, _ = B.weights(8, sch["steps"], sch["free_idx"], pairs)
+    return list(sch["steps"]), w
+
+
+def test_workspace_bytes_formula():
+    steps, w = _cfg2()
+    nb = _plan(B.ACOUSTIC2D, (64, 32), 8, steps, w, 1e-3)
+    pts = 64 * 32 * 3
+    assert nb == pts * 8 + 2 * 6 * pts * 8
+
+
+def test_plan_stability_limit_is_sharp():
+    steps, w = _cfg2()
+    n = 256
+    lim = workloads.stable_H(workloads.ISB_ORDER8_K6, 1.0, 1.0 / n, 2, workloads.SIGMA_FD4, 1.0)
+    _plan(B.ACOUSTIC2D, (n, n), 8, steps, w, 0.999 * lim)
+    with pytest.raises(B.GBSError) as e:
+        _plan(B.ACOUSTIC2D, (n, n), 8, steps, w, 1.002 * lim)
+    assert e.value.status == B.GBS_EUNSTABLE
+    # flag turns the check off
+    _plan(B.ACOUSTIC2D, (n, n), 8, steps, w, 2 * lim, flags=B.FLAG_NO_STABILITY_CHECK)
+
+
+def test_plan_rejects_order_2_mod_4_and_bad_weights():
+    w6 = W.to_fp64(W.weights(6, [2, 4, 6]))
+    with pytest.raises(B.GBSError) as e:
+        _plan(B.ADVECT1D, (64,), 6, [2, 4, 6], w6, 1e-3)
+    assert e.value.status == B.GBS_EORDER
+    steps, w = _cfg2()
+    bad = list(w)
+    bad[0] += 1e-6
+    with pytest.raises(B.GBSError) as e:
+        _plan(B.ACOUSTIC2D, (64, 64), 8, steps, bad, 1e-4)
+    assert e.value.status == B.GBS_EORDER
+
+
+@pytest.mark.parametrize("kw", [dict(n=(4, 64)), dict(n=(64, 64), fd_order=6),
+                                dict(n=(64, 64), n_rhs=0), dict(n=(64, 64), dtype=7),
+                                dict(n=(64, 64), c2=-1.0)])
+def test_plan_rejects_bad_problem(kw):
+    steps, w = _cfg2()
+    n = kw.pop("n")
+    with pytest.raises(B.GBSError) as e:
+        _plan(B.ACOUSTIC2D, n, 8, steps, w, 1e-5, **kw)
+    assert e.value.status in (B.GBS_EINVAL, B.GBS_EUNSUPPORTED)
+
+
+def test_plan_rejects_small_or_misaligned_workspace():
+    steps, w = _cfg2()
+    pr = B.make_problem(B.ACOUSTIC2D, (64, 64))
+    sc = B.make_scheme(8, steps, w)
+    nb = B.workspace_bytes(pr, sc)
+    with pytest.raises(B.GBSError) as e:
+        B.plan_create(pr, sc, 1e-4, FAKE_WS, nb - 1)
+    assert e.value.status == B.GBS_ENOMEM
+    with pytest.raises(B.GBSError) as e:
+        B.plan_create(pr, sc, 1e-4, FAKE_WS + 8, nb)
+    assert e.value.status == B.GBS_EINVAL
