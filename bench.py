@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (the reference "
+                         "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method's data-parallel path is "
@@ -78,6 +81,15 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes_read=src.numel() * 8, copy_bytes_written=dst.numel() * 8,
+                              launches=5)), flush=True)
+        return
     from paper_1907_11771_amd import binding as B
     from paper_1907_11771_amd.plan import GBSPlan, scheme_weights
     from synth import fields, workloads

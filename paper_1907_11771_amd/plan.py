@@ -30,6 +30,10 @@ class GBSPlan:
         if not torch.cuda.is_available():
             raise RuntimeError("GBSPlan needs a HIP device; there is no CPU path")
         self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("GBSPlan runs on a HIP device, not %s" % self.device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = dtype
         self.op, self.n, self.n_rhs = op, tuple(int(x) for x in n), n_rhs
         self.H = float(H)
