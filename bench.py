@@ -4,9 +4,9 @@ MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-One "step" is one macro step: the shared first evaluation, all leap-frog
-sweeps of the six sequences, the averaging and the FP64 combination
-(1 + sum N_j = 43 RHS evaluations per grid point).  Prints one JSON line.
+One "step" is one macro step: all six GBS sequences (forward Euler, N_j
+leap-frog steps, averaging) and the FP64 weighted combination, i.e.
+1 + sum N_j = 43 RHS evaluations per grid point.  Prints one JSON line.
 """
 import argparse
 import json
@@ -18,32 +18,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+STREAM_BYTES_PER_UPDATE = 72.0   # FP64 2-D acoustic leap-frog update, streaming: 3 F b
 
 
-def lf_bytes_per_macro_step(steps, points, fields, b):
-    """Algorithmic bytes of the leap-frog launches of one macro step
-    (streaming form): a step that stores its level reads y_{s-1}, y_s and
-    writes y_{s+1} (3 F b per point); a sequence's last step reads y_{N-1},
-    y_N and writes (first to finish) or reads and writes (the others) the
-    FP64 accumulator, or writes y_out (the last)."""
-    order = sorted(steps)
-    tot = 0
-    for r, n in enumerate(order):
-        tot += (n - 1) * 3 * fields * b * points
-        last = 2 * fields * b
-        if r == 0:
-            last += fields * 8
-        elif r == len(order) - 1:
-            last += fields * 8 + fields * b
-        else:
-            last += 2 * fields * 8
-        tot += last * points
-    return tot
-
-
-def first_bytes_per_macro_step(k, points, fields, b):
-    """Shared first evaluation: reads y_0, writes y_1 of every sequence."""
-    return (1 + k) * fields * b * points
+def kernel_names(variant, B):
+    step = {B.VARIANT_TEMPORAL: "gbs::pass2d<double, 4, 7, false>",
+            B.VARIANT_TEMPORAL4: "gbs::pass2d<double, 4, 4, false>",
+            B.VARIANT_TEMPORAL_S5: "gbs::pass2d<double, 4, 5, true>",
+            B.VARIANT_TEMPORAL_S6: "gbs::pass2d<double, 4, 6, true>",
+            B.VARIANT_FLAT: "gbs::lf_kernel<double, 4, 2>"}.get(variant,
+                                                              "gbs::lf_march2d<double, 4, ...>")
+    temporal = variant in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
+                           B.VARIANT_TEMPORAL_S6)
+    aux = "gbs::combine_kernel<double>" if temporal else "gbs::first_kernel<double, 4, 2>"
+    return step, aux
 
 
 def cpu_baseline(cfg, y0):
@@ -61,7 +49,8 @@ def cpu_baseline(cfg, y0):
     dt = time.perf_counter() - t
     updates = cfg["n"] * cfg["n"] * (1 + sum(steps))
     return dict(value=updates / dt, unit="grid-pt RHS updates/s", cores=1, kind="oracle",
-                sample="1 macro step of the same 2048^2 FP64 workload (43 sweeps), %.1f s" % dt)
+                sample="1 macro step of the same 2048^2 FP64 workload (43 RHS sweeps), "
+                       "%.1f s, NumPy single thread" % dt)
 
 
 def main():
@@ -70,6 +59,10 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="stepping-kernel variant (0 = the library's choice)")
+    ap.add_argument("--band", type=int, default=0,
+                    help="rows per band of the temporally blocked passes (0 = default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -79,7 +72,6 @@ def main():
               "benchmarked on a single MI355X (--gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
@@ -90,6 +82,7 @@ def main():
         print(json.dumps(dict(copy_bytes_read=src.numel() * 8, copy_bytes_written=dst.numel() * 8,
                               launches=5)), flush=True)
         return
+
     from paper_1907_11771_amd import binding as B
     from paper_1907_11771_amd.plan import GBSPlan, scheme_weights
     from synth import fields, workloads
@@ -101,20 +94,24 @@ def main():
     dev = torch.device("cuda:0")
     plan = GBSPlan(B.ACOUSTIC2D, (n, n), cfg["scheme"]["p"], steps, w, cfg["H"], fd_order=4,
                    dtype=torch.float64, c2=cfg["c2"], device=dev)
+    if args.variant:
+        plan.set_variant(args.variant)
+    if args.band:
+        B.check(B.lib().gbs_plan_set_band(plan.handle, args.band))
     y = torch.from_numpy(y0[None]).to(dev)
     out = torch.empty_like(y)
 
     plan.step(y, out, n_macro=args.warmup)
     torch.cuda.synchronize()
-    # timed region: K macro steps, every launch bracketed by HIP events on the
-    # plan's stream (created beforehand)
+    # timed region: K macro steps; every launch is bracketed by HIP events on
+    # the plan's stream (events created beforehand)
     plan.set_timing(max(args.steps, 2))
     torch.cuda.synchronize()
     t = time.perf_counter()
     plan.step(y, out, n_macro=args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    lf_ms, lf_n, first_ms, first_n = plan.get_timing()
+    step_ms, step_n, aux_ms, aux_n = plan.get_timing()
     plan.set_timing(0)
     # the same K steps without events, to show what the events cost
     torch.cuda.synchronize()
@@ -123,10 +120,12 @@ def main():
     torch.cuda.synchronize()
     dt_plain = time.perf_counter() - t
 
+    variant = plan.variant()
+    kstep, kaux = kernel_names(variant, B)
     upd = plan.updates_per_macro_step() * args.steps
-    pts = n * n
-    lf_bytes = lf_bytes_per_macro_step(steps, pts, 3, 8) * args.steps
-    achieved = lf_bytes / (lf_ms * 1e-3) / 1e9
+    sb, sl, ab, al = plan.algorithmic_bytes()
+    step_bytes = sb * args.steps
+    achieved = step_bytes / (step_ms * 1e-3) / 1e9
     rec = dict(
         metric="grid-pt RHS updates/s",
         value=upd / dt,
@@ -137,16 +136,19 @@ def main():
         dtype="f64", data="synthetic",
         config=dict(workload=cfg["name"], grid=[n, n], fields=3, fd_order=4,
                     scheme_order=8, sequences=steps, evals_per_macro_step=1 + sum(steps),
-                    H=cfg["H"], macro_steps_timed=args.steps),
+                    H=cfg["H"], macro_steps_timed=args.steps, kernel_variant=variant),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=None,
-                      kernel="lf_kernel<double, 4, 2>",
-                      avg_launch_us=lf_ms * 1e3 / max(lf_n, 1), launches=lf_n,
-                      algorithmic_bytes_per_launch=lf_bytes / max(lf_n, 1)),
+                      frac=achieved / HBM_PEAK_GBS, traffic=None, kernel=kstep,
+                      avg_launch_us=step_ms * 1e3 / max(step_n, 1), launches=step_n,
+                      algorithmic_bytes_per_launch=step_bytes / max(step_n, 1)),
+        # the streaming form must move 72 B per update; this is the rate those
+        # bytes would need, i.e. the fraction of the streaming roofline reached
+        streaming_equivalent=dict(bytes_per_update=STREAM_BYTES_PER_UPDATE,
+                                  gbps=upd * STREAM_BYTES_PER_UPDATE / dt / 1e9,
+                                  frac=upd * STREAM_BYTES_PER_UPDATE / dt / 1e9 / HBM_PEAK_GBS),
         ms_per_step_without_events=dt_plain * 1e3 / args.steps,
-        first_kernel=dict(avg_launch_us=first_ms * 1e3 / max(first_n, 1),
-                          gbps=first_bytes_per_macro_step(len(steps), pts, 3, 8) * args.steps
-                          / (first_ms * 1e-3) / 1e9 if first_ms else None),
+        aux_kernel=dict(kernel=kaux, avg_launch_us=aux_ms * 1e3 / max(aux_n, 1),
+                        gbps=ab * args.steps / (aux_ms * 1e-3) / 1e9 if aux_ms else None),
     )
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(cfg, y0)

@@ -123,8 +123,9 @@ int gbs_isb(int32_t k, const int32_t* steps, const double* weights, double* isb_
 
 /*
  * gbs_plan_workspace_bytes — device workspace needed by a plan: one FP64
- * accumulator state plus two levels per sequence in the plan's dtype,
- * each 256-byte aligned.
+ * accumulator state plus, per sequence, two levels in the plan's dtype
+ * (four for GBS_ACOUSTIC2D, whose temporally blocked passes read one pair
+ * and write the other), each 256-byte aligned.
  */
 int gbs_plan_workspace_bytes(const gbs_problem* prob, const gbs_scheme* sch, size_t* bytes);
 
@@ -165,16 +166,68 @@ int gbs_plan_set_sources(gbs_plan* plan, int32_t n_src, const int32_t* rhs,
 int gbs_step(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void* y_out);
 
 /*
+ * gbs_plan_set_variant — choose the leap-frog kernel (all variants compute
+ * the same values in the same order; they differ in work layout only):
+ *   GBS_VARIANT_AUTO        library's choice (default)
+ *   GBS_VARIANT_FLAT        one grid point per thread (every operator)
+ *   GBS_VARIANT_MARCH8/16   2-D acoustic only: each thread marches 8 / 16
+ *                           rows, y-stencil rows kept in registers
+ *   GBS_VARIANT_MARCH8/16_NT  as above with non-temporal level stores
+ *   GBS_VARIANT_TEMPORAL    2-D acoustic only: temporally blocked passes of
+ *                           up to 7 (FD4) / 3 (FD8) evaluations of f per
+ *                           launch, levels kept in registers; f(t_0, y_0) is
+ *                           evaluated once per sequence
+ *   GBS_VARIANT_TEMPORAL4   the same with at most 4 evaluations per pass
+ *   GBS_VARIANT_TEMPORAL_S5/S6  at most 5 / 6 evaluations per pass, the
+ *                           levels of one row step evaluated independently
+ *                           (one more row of time skew between levels)
+ * The temporally blocked variants agree with the streaming ones to
+ * rounding (the combination is summed in the same order, the products may
+ * be contracted differently).
+ * gbs_plan_get_variant returns the variant AUTO resolves to.
+ * gbs_plan_set_band sets the rows per band of the temporally blocked
+ * passes (default 64).
+ */
+enum {
+  GBS_VARIANT_AUTO = 0,
+  GBS_VARIANT_FLAT = 1,
+  GBS_VARIANT_MARCH8 = 2,
+  GBS_VARIANT_MARCH16 = 3,
+  GBS_VARIANT_MARCH8_NT = 4,
+  GBS_VARIANT_MARCH16_NT = 5,
+  GBS_VARIANT_TEMPORAL = 6,
+  GBS_VARIANT_TEMPORAL4 = 7,
+  GBS_VARIANT_TEMPORAL_S5 = 8,
+  GBS_VARIANT_TEMPORAL_S6 = 9
+};
+int gbs_plan_set_variant(gbs_plan* plan, int32_t variant);
+int gbs_plan_set_band(gbs_plan* plan, int32_t rows);
+int gbs_plan_get_variant(const gbs_plan* plan, int32_t* variant);
+
+/*
  * gbs_plan_set_timing — enabled != 0: every kernel launch is bracketed by HIP
  * events on the plan's stream, and gbs_plan_get_timing() returns the summed
- * duration (ms) and the launch count of the leap-frog kernel and of the
- * first-evaluation kernel since the last reset (the read synchronises the
- * stream and resets).  enabled > 1 also creates the events for that many
- * macro steps up front.  enabled = 0 turns timing off.
+ * duration (ms) and the launch count of the stepping kernel (streaming
+ * leap-frog sweeps, or temporally blocked passes) and of the auxiliary
+ * kernel (the shared first evaluation, or the final combination) since the
+ * last reset (the read synchronises the stream and resets).  enabled > 1
+ * also creates the events for that many macro steps up front.  enabled = 0
+ * turns timing off.
  */
 int gbs_plan_set_timing(gbs_plan* plan, int32_t enabled);
-int gbs_plan_get_timing(gbs_plan* plan, double* lf_ms, int64_t* lf_launches,
-                        double* first_ms, int64_t* first_launches);
+int gbs_plan_get_timing(gbs_plan* plan, double* step_ms, int64_t* step_launches,
+                        double* aux_ms, int64_t* aux_launches);
+
+/*
+ * gbs_plan_algorithmic_bytes — HBM bytes one macro step must move with the
+ * plan's current variant, per kernel class (stepping kernel / auxiliary
+ * kernel, as in gbs_plan_get_timing), and the launches of each per macro
+ * step: every level, y*, accumulator or state each kernel reads or writes
+ * once over the grid; halo re-reads and redundant edge work are not
+ * counted.  For measurement only.
+ */
+int gbs_plan_algorithmic_bytes(const gbs_plan* plan, double* step_bytes, int64_t* step_launches,
+                               double* aux_bytes, int64_t* aux_launches);
 
 /* Updates (grid point x RHS x f-evaluation) one macro step performs. */
 int gbs_plan_updates_per_macro_step(const gbs_plan* plan, double* updates);

@@ -16,6 +16,9 @@ GBS_ESINGULAR, GBS_EUNSTABLE, GBS_EDEVICE, GBS_ENOMEM, GBS_EUNSUPPORTED = -4, -5
 ADVECT1D, ACOUSTIC2D, ACOUSTIC3D = 1, 2, 3
 F32, F64 = 1, 2
 FLAG_NO_STABILITY_CHECK = 1
+VARIANT_AUTO, VARIANT_FLAT, VARIANT_MARCH8, VARIANT_MARCH16 = 0, 1, 2, 3
+VARIANT_MARCH8_NT, VARIANT_MARCH16_NT = 4, 5
+VARIANT_TEMPORAL, VARIANT_TEMPORAL4, VARIANT_TEMPORAL_S5, VARIANT_TEMPORAL_S6 = 6, 7, 8, 9
 MAX_SEQ = 16
 MAX_SRC = 16
 
@@ -69,8 +72,12 @@ def lib():
             "gbs_plan_set_sources": [vp, i32, P(i32), P(i64), P(dbl), dbl, dbl],
             "gbs_step": [vp, dbl, i32, vp, vp],
             "gbs_plan_set_timing": [vp, i32],
+            "gbs_plan_set_variant": [vp, i32],
+            "gbs_plan_get_variant": [vp, P(i32)],
+            "gbs_plan_set_band": [vp, i32],
             "gbs_plan_get_timing": [vp, P(dbl), P(i64), P(dbl), P(i64)],
             "gbs_plan_updates_per_macro_step": [vp, P(dbl)],
+            "gbs_plan_algorithmic_bytes": [vp, P(dbl), P(i64), P(dbl), P(i64)],
             "gbs_plan_destroy": [vp],
         }
         for name, args in sig.items():

@@ -110,6 +110,103 @@ __global__ __launch_bounds__(256) void lf_kernel(const StepArgs<T> a) {
   }
 }
 
+// Store that does not keep the line in the caches (the level written now is
+// read again only one or two launches later, after the whole grid has
+// streamed through).
+template <bool NT, typename T>
+__device__ __forceinline__ void store(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Workgroup index -> tile index so that each of the 8 XCDs (which receive
+// workgroups round-robin) works on one contiguous band of tiles, keeping the
+// stencil's neighbour rows in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  if (nblocks % 8) return b;
+  return (b % 8) * (nblocks / 8) + b / 8;
+}
+
+// 2-D acoustic leap-frog sweep, marching in y: a 256-thread block covers 64
+// columns x 4 strips of TY rows; every thread walks down its column keeping
+// the rows y-R..y+R of p and v_y in registers (the y-derivatives), while the
+// x-derivatives read the current row (cache-resident across the wavefront).
+// Same arithmetic, in the same order, as lf_kernel.
+template <typename T, int ORDER, int TY, bool NT>
+__global__ __launch_bounds__(256) void lf_march2d(const StepArgs<T> a) {
+  constexpr int R = Fd<ORDER>::R;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int ntx = (nx + 63) >> 6;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int x = tx * 64 + (threadIdx.x & 63);
+  const int y0 = ty * 4 * TY + (threadIdx.x >> 6) * TY;
+  if (x >= nx || y0 >= ny) return;
+  const SeqDesc<T>& d = a.seq[blockIdx.y];
+  const int64_t rhs = blockIdx.z;
+  const int64_t base = rhs * a.g.state;
+  const int64_t F1 = a.g.field, F2 = 2 * a.g.field;
+  const T* __restrict__ cp = d.cur + base;
+  const T* __restrict__ cvx = cp + F1;
+  const T* __restrict__ cvy = cp + F2;
+  T pw[2 * R + 1], vw[2 * R + 1];
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {
+    const int64_t row = (int64_t)wrap(y0 - R + k, ny) * nx + x;
+    pw[k] = cp[row];
+    vw[k] = cvy[row];
+  }
+#pragma unroll
+  for (int i = 0; i < TY; ++i) {
+    const int y = y0 + i;
+    if (y >= ny) break;
+    {
+      const int64_t row = (int64_t)wrap(y + R, ny) * nx + x;
+      pw[2 * R] = cp[row];
+      vw[2 * R] = cvy[row];
+    }
+    const int64_t rowoff = (int64_t)y * nx;
+    T syp = T(0), syv = T(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      syp += Fd<ORDER>::template w<T>(k) * (pw[R + 1 + k] - pw[R - 1 - k]);
+      syv += Fd<ORDER>::template w<T>(k) * (vw[R + 1 + k] - vw[R - 1 - k]);
+    }
+    const T sxp = dsum<T, ORDER>(cp + rowoff, x, nx, 1);
+    const T sxv = dsum<T, ORDER>(cvx + rowoff, x, nx, 1);
+    const T c2 = a.c2f ? a.c2f[rowoff + x] : a.c2c;
+    const T dvx = a.invx * sxv;
+    const T dvy = a.invy * syv;
+    T f[3];
+    f[0] = -(c2 * (dvx + dvy));
+    f[1] = -(a.invx * sxp);
+    f[2] = -(a.invy * syp);
+    const int64_t idx = rowoff + x;
+    if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int64_t e = base + q * F1 + idx;
+      const T o = d.old[e];
+      const T nw = o + d.h2 * f[q];
+      if (!(d.mode & MODE_LAST)) {
+        store<NT>(d.out + e, nw);
+      } else {
+        const T c = q == 0 ? pw[R] : (q == 1 ? cvx[idx] : vw[R]);
+        const double ys = 0.25 * (((double)o + 2.0 * (double)c) + (double)nw);
+        double v = d.cw * ys;
+        if (!(d.mode & MODE_FIRST)) v = a.acc[e] + v;
+        if (d.mode & MODE_FINAL) store<NT>(a.yout + e, (T)v);
+        else store<NT>(a.acc + e, v);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+      pw[k] = pw[k + 1];
+      vw[k] = vw[k + 1];
+    }
+  }
+}
+
 template <typename T, int ORDER, int OP>
 __global__ __launch_bounds__(256) void first_kernel(const FirstArgs<T> a) {
   constexpr int F = NFields<OP>::F;

@@ -24,6 +24,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "temporal.hpp"
 
 namespace gbs {
 
@@ -64,6 +65,12 @@ struct gbs_plan {
   int nsrc = 0;
   SrcDesc src[GBS_MAX_SRC];
   double f0 = 0, delay = 0;
+  // leap-frog kernel variant (GBS_VARIANT_*) and rows per band of the
+  // temporally blocked passes
+  int variant = 0;
+  int band = 64;
+  // temporally blocked layout: per sequence two pairs of levels
+  void* pair[GBS_MAX_SEQ][2][2];
   // timing
   bool timing = false;
   std::vector<EventPair> lf_ev, first_ev;
@@ -134,10 +141,15 @@ int validate_scheme(const gbs_scheme* s) {
   return GBS_OK;
 }
 
+// levels per sequence: two for the streaming sweeps; the 2-D operator also
+// has the temporally blocked passes, which read one pair of levels and
+// write the other (and the FP64 y* into a free pair at the end)
+int levels_per_seq(const gbs_problem* p) { return p->op == GBS_ACOUSTIC2D ? 4 : 2; }
+
 size_t workspace_bytes(const gbs_problem* p, int k) {
   const int64_t pts = p->n[0] * p->n[1] * p->n[2];
   const size_t elems = (size_t)p->n_rhs * fields_of(p->op) * pts;
-  return align_up(elems * 8) + 2 * (size_t)k * align_up(elems * dsize(p->dtype));
+  return align_up(elems * 8) + levels_per_seq(p) * (size_t)k * align_up(elems * dsize(p->dtype));
 }
 
 double ricker(double t, double f0, double delay) {
@@ -170,6 +182,119 @@ void fill_geometry(const gbs_plan* P, Geometry& g, T& c2c, const T*& c2f, T& ix,
   iz = (T)((double)P->prob.n[2] / den);
   c2c = (T)(P->prob.op == GBS_ADVECT1D ? 1.0 : P->prob.c2);
   c2f = (const T*)P->prob.c2_field;
+}
+
+int resolve_variant(const gbs_plan* P) {
+  if (P->variant != GBS_VARIANT_AUTO) return P->variant;
+  if (P->prob.op == GBS_ACOUSTIC2D) return GBS_VARIANT_TEMPORAL;
+  return GBS_VARIANT_FLAT;
+}
+
+bool is_temporal(int v) { return v >= GBS_VARIANT_TEMPORAL && v <= GBS_VARIANT_TEMPORAL_S6; }
+
+template <typename T, int ORDER, int G, bool SKEW1>
+int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
+  constexpr int R = Fd<ORDER>::R;
+  // split the N_j + 1 evaluations of every sequence into passes of at most G
+  int npass[GBS_MAX_SEQ], gsz[GBS_MAX_SEQ][32];
+  int maxpass = 0;
+  for (int j = 0; j < P->k; ++j) {
+    const int E = P->steps[j] + 1;
+    const int np = (E + G - 1) / G;
+    if (np > 32) return fail(GBS_EUNSUPPORTED, "too many passes");
+    npass[j] = np;
+    for (int q = 0; q < np; ++q) gsz[j][q] = E / np + (q < E % np ? 1 : 0);
+    maxpass = std::max(maxpass, np);
+  }
+  PassArgs<T> pa;
+  std::memset(&pa, 0, sizeof(pa));
+  T c2c, invz;
+  fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
+  pa.c2c = c2c;
+  std::memcpy(pa.src, P->src, sizeof(P->src));
+  pa.band = P->band;
+  pa.nbands = (int)((P->prob.n[1] + P->band - 1) / P->band);
+  const int nx = (int)P->prob.n[0];
+  CombineArgs<T> ca;
+  std::memset(&ca, 0, sizeof(ca));
+  ca.k = P->k;
+  ca.n = (int64_t)P->prob.n_rhs * P->state;
+  ca.yout = yout;
+  for (int r = 0; r < P->k; ++r) {
+    const int j = P->order[r];
+    ca.c[r] = P->w[j];
+    ca.ystar[r] = (const double*)P->pair[j][(npass[j] - 1) % 2 == 0 ? 0 : 1][0];
+  }
+  for (int m = 0; m < n_macro; ++m) {
+    const double t = t0 + m * P->H;
+    const T* y0 = m == 0 ? yin : yout;
+    for (int q = 0; q < maxpass; ++q) {
+      int n = 0, maxs = 0;
+      for (int r = 0; r < P->k; ++r) {
+        const int j = P->order[r];
+        if (q >= npass[j]) continue;
+        PassSeq<T>& d = pa.seq[n++];
+        const double h = P->H / P->steps[j];
+        int s0 = 0;             // the pass's input level is y_{s0}: s0 = evaluations so far
+        for (int qq = 0; qq < q; ++qq) s0 += gsz[j][qq];
+        d.g = gsz[j][q];
+        d.h = (T)h;
+        d.flags = (q == 0 ? PASS_FIRST : 0) | (q == npass[j] - 1 ? PASS_FINAL : 0);
+        d.cur = q == 0 ? y0 : (const T*)P->pair[j][(q - 1) % 2][1];
+        d.old = q == 0 ? nullptr : (const T*)P->pair[j][(q - 1) % 2][0];
+        d.out_a = (T*)P->pair[j][q % 2][0];
+        d.out_b = (T*)P->pair[j][q % 2][1];
+        d.ystar = (double*)P->pair[j][q % 2][0];
+        d.strips = (nx + (64 - 2 * d.g * R) - 1) / (64 - 2 * d.g * R);
+        for (int e = 0; e < d.g; ++e)
+          d.amp[e] = P->nsrc ? ricker(t + (s0 + e) * h, P->f0, P->delay) : 0.0;
+        maxs = std::max(maxs, d.strips);
+      }
+      pa.max_strips = maxs;
+      const unsigned waves = (unsigned)maxs * pa.nbands;
+      EventPair* ev = nullptr;
+      if (P->timing) {
+        ev = &next_event(P->lf_ev, P->lf_used);
+        hipEventRecord(ev->a, P->stream);
+      }
+      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1>), dim3((waves + 3) / 4, n, P->prob.n_rhs),
+                         dim3(256), 0, P->stream, pa);
+      if (ev) hipEventRecord(ev->b, P->stream);
+    }
+    EventPair* ev = nullptr;
+    if (P->timing) {
+      ev = &next_event(P->first_ev, P->first_used);
+      hipEventRecord(ev->a, P->stream);
+    }
+    hipLaunchKernelGGL((combine_kernel<T>), dim3((unsigned)((ca.n + 255) / 256)), dim3(256), 0,
+                       P->stream, ca);
+    if (ev) hipEventRecord(ev->b, P->stream);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GBS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return GBS_OK;
+}
+
+template <typename T, int ORDER, int TY, bool NT>
+void launch_march2d(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gz) {
+  const int ntx = (int)((P->prob.n[0] + 63) / 64);
+  const int nty = (int)((P->prob.n[1] + 4 * TY - 1) / (4 * TY));
+  hipLaunchKernelGGL((lf_march2d<T, ORDER, TY, NT>), dim3(ntx * nty, n, gz), dim3(256), 0,
+                     P->stream, sa);
+}
+
+template <typename T, int ORDER, int OP>
+void launch_lf(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gx, unsigned gz) {
+  if constexpr (OP == OP_AC2D) {
+    switch (resolve_variant(P)) {
+      case GBS_VARIANT_MARCH8: launch_march2d<T, ORDER, 8, false>(P, sa, n, gz); return;
+      case GBS_VARIANT_MARCH16: launch_march2d<T, ORDER, 16, false>(P, sa, n, gz); return;
+      case GBS_VARIANT_MARCH8_NT: launch_march2d<T, ORDER, 8, true>(P, sa, n, gz); return;
+      case GBS_VARIANT_MARCH16_NT: launch_march2d<T, ORDER, 16, true>(P, sa, n, gz); return;
+      default: break;
+    }
+  }
+  hipLaunchKernelGGL((lf_kernel<T, ORDER, OP>), dim3(gx, n, gz), dim3(256), 0, P->stream, sa);
 }
 
 template <typename T, int ORDER, int OP>
@@ -230,7 +355,7 @@ int run(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         ev = &next_event(P->lf_ev, P->lf_used);
         hipEventRecord(ev->a, P->stream);
       }
-      hipLaunchKernelGGL((lf_kernel<T, ORDER, OP>), dim3(gx, n, gz), dim3(block), 0, P->stream, sa);
+      launch_lf<T, ORDER, OP>(P, sa, n, gx, gz);
       if (ev) hipEventRecord(ev->b, P->stream);
     }
   }
@@ -244,6 +369,16 @@ int dispatch_order(gbs_plan* P, double t0, int n, const void* yin, void* yout) {
   const T* a = (const T*)yin;
   T* b = (T*)yout;
   const int op = P->prob.op;
+  const int v = resolve_variant(P);
+  if (op == GBS_ACOUSTIC2D && is_temporal(v)) {
+    if (P->prob.fd_order == 8) return run_temporal<T, 8, 3, true>(P, t0, n, a, b);
+    switch (v) {
+      case GBS_VARIANT_TEMPORAL4: return run_temporal<T, 4, 4, false>(P, t0, n, a, b);
+      case GBS_VARIANT_TEMPORAL_S5: return run_temporal<T, 4, 5, true>(P, t0, n, a, b);
+      case GBS_VARIANT_TEMPORAL_S6: return run_temporal<T, 4, 6, true>(P, t0, n, a, b);
+      default: return run_temporal<T, 4, 7, false>(P, t0, n, a, b);
+    }
+  }
   if (P->prob.fd_order == 4) {
     if (op == GBS_ADVECT1D) return run<T, 4, OP_ADV1D>(P, t0, n, a, b);
     if (op == GBS_ACOUSTIC2D) return run<T, 4, OP_AC2D>(P, t0, n, a, b);
@@ -314,11 +449,15 @@ extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gb
     char* base = (char*)workspace;
     P->acc = (double*)base;
     base += align_up(elems * 8);
-    for (int j = 0; j < P->k; ++j)
-      for (int l = 0; l < 2; ++l) {
-        P->lev[j][l] = base;
-        base += align_up(elems * dsize(prob->dtype));
-      }
+    const size_t lb = align_up(elems * dsize(prob->dtype));
+    for (int j = 0; j < P->k; ++j) {
+      char* sb = base + (size_t)j * levels_per_seq(prob) * lb;
+      P->lev[j][0] = sb;
+      P->lev[j][1] = sb + lb;
+      if (levels_per_seq(prob) == 4)
+        for (int q = 0; q < 2; ++q)
+          for (int l = 0; l < 2; ++l) P->pair[j][q][l] = sb + (2 * q + l) * lb;
+    }
     *out = P;
     return GBS_OK;
   } catch (const std::exception& e) {
@@ -368,6 +507,29 @@ extern "C" int gbs_step(gbs_plan* P, double t0, int32_t n_macro, const void* y_i
   return dispatch_order<float>(P, t0, n_macro, y_in, y_out);
 }
 
+extern "C" int gbs_plan_set_variant(gbs_plan* P, int32_t variant) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  if (variant < GBS_VARIANT_AUTO || variant > GBS_VARIANT_TEMPORAL_S6)
+    return fail(GBS_EINVAL, "unknown variant %d", variant);
+  if (variant >= GBS_VARIANT_MARCH8 && P->prob.op != GBS_ACOUSTIC2D)
+    return fail(GBS_EUNSUPPORTED, "this variant is built for the 2-D acoustic operator only");
+  P->variant = variant;
+  return GBS_OK;
+}
+
+extern "C" int gbs_plan_set_band(gbs_plan* P, int32_t rows) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  if (rows < 1 || rows > (1 << 20)) return fail(GBS_EINVAL, "rows per band out of range");
+  P->band = rows;
+  return GBS_OK;
+}
+
+extern "C" int gbs_plan_get_variant(const gbs_plan* P, int32_t* variant) {
+  if (!P || !variant) return fail(GBS_EINVAL, "null argument");
+  *variant = resolve_variant(P);
+  return GBS_OK;
+}
+
 extern "C" int gbs_plan_set_timing(gbs_plan* P, int32_t enabled) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
   if (enabled < 0) return fail(GBS_EINVAL, "enabled must be >= 0");
@@ -401,6 +563,56 @@ extern "C" int gbs_plan_get_timing(gbs_plan* P, double* lf_ms, int64_t* lf_n, do
   if (first_ms) *first_ms = sum(P->first_ev, P->first_used);
   if (first_n) *first_n = (int64_t)P->first_used;
   P->lf_used = P->first_used = 0;
+  return GBS_OK;
+}
+
+// Algorithmic HBM bytes of one macro step, per kernel class, for the variant
+// in use: every level or accumulator a kernel must read or write once over
+// the grid (halo re-reads and redundant edge work are not counted).
+extern "C" int gbs_plan_algorithmic_bytes(const gbs_plan* P, double* step_bytes,
+                                          int64_t* step_launches, double* aux_bytes,
+                                          int64_t* aux_launches) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  const double pts = (double)P->field * P->prob.n_rhs;
+  const double Fb = (double)P->F * dsize(P->prob.dtype);   // one level, per point
+  const double F8 = (double)P->F * 8.0;                     // one FP64 state, per point
+  const int v = resolve_variant(P);
+  double sb = 0, ab = 0;
+  int64_t sl = 0, al = 0;
+  if (P->prob.op == GBS_ACOUSTIC2D && is_temporal(v)) {
+    const int G = v == GBS_VARIANT_TEMPORAL4 ? 4 : v == GBS_VARIANT_TEMPORAL_S5 ? 5
+                : v == GBS_VARIANT_TEMPORAL_S6 ? 6 : (P->prob.fd_order == 8 ? 3 : 7);
+    const int Gx = P->prob.fd_order == 8 ? 3 : G;
+    int maxpass = 0;
+    for (int j = 0; j < P->k; ++j) {
+      const int E = P->steps[j] + 1, np = (E + Gx - 1) / Gx;
+      maxpass = std::max(maxpass, np);
+      for (int q = 0; q < np; ++q) {
+        sb += (q == 0 ? Fb : 2 * Fb) * pts;                  // inputs
+        sb += (q == np - 1 ? F8 : 2 * Fb) * pts;             // outputs
+      }
+    }
+    sl = maxpass;
+    ab = ((double)P->k * F8 + Fb) * pts;                     // combine
+    al = 1;
+  } else {
+    for (int r = 0; r < P->k; ++r) {
+      const int N = P->steps[P->order[r]];
+      sb += (N - 1) * 3 * Fb * pts;
+      double last = 2 * Fb;
+      if (r == 0) last += F8;
+      else if (r == P->k - 1) last += F8 + Fb;
+      else last += 2 * F8;
+      sb += last * pts;
+    }
+    sl = P->nmax;
+    ab = (1 + P->k) * Fb * pts;                              // first evaluation
+    al = 1;
+  }
+  if (step_bytes) *step_bytes = sb;
+  if (step_launches) *step_launches = sl;
+  if (aux_bytes) *aux_bytes = ab;
+  if (aux_launches) *aux_launches = al;
   return GBS_OK;
 }
 

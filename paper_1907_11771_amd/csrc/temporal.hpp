@@ -1,0 +1,276 @@
+// Temporally blocked GBS sequence passes for the 2-D acoustic operator.
+//
+// A pass advances one sequence by up to G evaluations of f in one launch, so
+// that the intermediate levels never leave the chip.  The first pass of a
+// sequence starts from y_0 and performs the forward Euler step (Sect. 2.1,
+// eq. GBS; the evaluation f(t_0, y_0) is repeated per sequence, which the
+// paper allows in place of sharing it, Sect. 3.6); later passes start from
+// the two levels the previous pass stored.  The last pass applies the
+// averaging y* = (y_{N-1} + 2 y_N + y_{N+1}) / 4 and stores y* in FP64; a
+// separate kernel forms sum_j c_j y*_j in ascending N (Sect. 3.2).
+//
+// Work layout: one wavefront owns a strip of 64 consecutive columns and a
+// band of rows, and marches down the band.  Level A_e (e = 0 is the pass's
+// input level) is produced e*R rows behind the input front (time skew), so
+// that every stencil input of A_e already exists.  Each lane keeps, for
+// every level, the last 2R+1 rows of (p, v_x, v_y) of its column in
+// registers (y-neighbours); x-neighbours come from the adjacent lanes by
+// cross-lane moves.  The lanes next to the strip edges receive no valid
+// neighbour data, so A_e is exact only on lanes [e*R, 64 - e*R): a pass of
+// g evaluations stores the 64 - 2 g R inner columns, and consecutive strips
+// overlap by 2 g R columns.
+#pragma once
+
+#include "stencil.hpp"
+
+namespace gbs {
+
+constexpr int PASS_FIRST = 1;   // input is y_0; evaluation 1 is forward Euler
+constexpr int PASS_FINAL = 2;   // output is y* (FP64) instead of two levels
+constexpr int PASS_GMAX = 8;
+
+template <typename T>
+struct PassSeq {
+  const T* old;       // later pass: y_{s-1}
+  const T* cur;       // later pass: y_s; first pass: y_0
+  T* out_a;           // non-final: A_{g-1}
+  T* out_b;           // non-final: A_g
+  double* ystar;      // final: y* (FP64, state-sized)
+  T h;                // substep h_j
+  int32_t g;          // evaluations in this pass (1..G)
+  int32_t flags;
+  int32_t strips;     // strips along x for this g
+  int32_t pad;
+  double amp[PASS_GMAX];  // source wavelet at each evaluation's time
+};
+
+template <typename T>
+struct PassArgs {
+  PassSeq<T> seq[GBS_MAX_SEQ];
+  SrcDesc src[GBS_MAX_SRC];
+  Geometry g;
+  const T* c2f;
+  T c2c;
+  T invx, invy;
+  int32_t band;       // rows per band
+  int32_t nbands;
+  int32_t max_strips;
+};
+
+// Cross-lane moves over the whole wavefront: lane l receives the value of
+// lane l+1 (from_right) or l-1 (from_left); the edge lane receives 0, which
+// only ever feeds the discarded halo lanes.
+template <int CTRL>
+__device__ __forceinline__ float lane_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_move(double v) {
+  return __longlong_as_double(
+      __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), CTRL, 0xF, 0xF, true));
+}
+constexpr int DPP_WAVE_SHL1 = 0x130;   // lane l <- lane l+1
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane l <- lane l-1
+
+// sum_k W_k (u(x+k) - u(x-k)) with u(x +/- k) gathered from the lanes
+// at distance k.
+template <typename T, int ORDER>
+__device__ __forceinline__ T lane_dsum(T u) {
+  constexpr int R = Fd<ORDER>::R;
+  T up = lane_move<DPP_WAVE_SHL1>(u), dn = lane_move<DPP_WAVE_SHR1>(u);
+  T s = Fd<ORDER>::template w<T>(0) * (up - dn);
+#pragma unroll
+  for (int k = 1; k < R; ++k) {
+    up = lane_move<DPP_WAVE_SHL1>(up);
+    dn = lane_move<DPP_WAVE_SHR1>(dn);
+    s += Fd<ORDER>::template w<T>(k) * (up - dn);
+  }
+  return s;
+}
+
+__device__ __forceinline__ int pmod(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+// r - d wrapped into [0, n) for 0 <= r < n, d >= 0 (wave-uniform operands)
+__device__ __forceinline__ int wrap_sub(int r, int d, int n) {
+  r -= d;
+  while (r < 0) r += n;
+  return r;
+}
+
+// One wavefront's pass over its strip and band.
+//
+// Time skew between consecutive levels: with SKEW1 = false level e is
+// produced R rows behind level e-1 and the levels of one row step are
+// evaluated in ascending order (each uses the row its predecessor has just
+// produced); with SKEW1 = true the skew is R+1 rows and the levels are
+// evaluated in descending order, so that all of them read only rows
+// produced in earlier row steps (independent work within a row step), at the
+// cost of one more window row per level.  The number of evaluations g of a
+// pass (at most G) is a runtime value, uniform over the wavefront.
+template <typename T, int ORDER, int G, bool SKEW1>
+__global__ __launch_bounds__(256) void pass2d(const PassArgs<T> a) {
+  constexpr int R = Fd<ORDER>::R;
+  constexpr int S = SKEW1 ? R + 1 : R;               // rows between consecutive levels
+  constexpr int P = SKEW1 ? 2 * R + 2 : 2 * R + 1;   // window rows per level
+  const PassSeq<T>& d = a.seq[blockIdx.y];
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int strip = wave % a.max_strips;
+  const int band = wave / a.max_strips;
+  if (strip >= d.strips || band >= a.nbands) return;
+  const int lane = threadIdx.x & 63;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int g = d.g;
+  const int halo = g * R;
+  const int wv = 64 - 2 * halo;
+  const int x0 = strip * wv;
+  const int col = x0 - halo + lane;                  // unwrapped column of this lane
+  const int gx = pmod(col, nx);
+  const bool lane_ok = lane >= halo && lane < 64 - halo && col < nx;
+  const int ya = band * a.band;
+  const int yb = min(ya + a.band, ny);
+  const int i0 = ya - halo;                          // first input row (A_0)
+  const int niter = (yb - ya) + halo + g * S;        // until A_g reaches row yb - 1
+  const int64_t rhs_base = (int64_t)blockIdx.z * a.g.state;
+  const int64_t F1 = a.g.field, F2 = 2 * a.g.field;
+  const bool first = d.flags & PASS_FIRST;
+  const bool final_ = d.flags & PASS_FINAL;
+  const bool varc = a.c2f != nullptr;
+  const bool srcs = a.g.nsrc > 0;
+  const T fac_lf = T(2) * d.h;
+  const T* __restrict__ cur = d.cur + rhs_base + gx;
+  const T* __restrict__ old = first ? cur : d.old + rhs_base + gx;
+
+  T W[G][P][3];
+#pragma unroll
+  for (int e = 0; e < G; ++e)
+#pragma unroll
+    for (int s = 0; s < P; ++s)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) W[e][s][q] = T(0);
+
+  int irow = pmod(i0, ny);                           // wrapped row of A_0 at this row step
+  for (int kb = 0; kb < niter; kb += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int k = kb + u;                          // row step; A_0 row i = i0 + k
+      // input rows: A_0 at row i, and for a later pass A_{-1} at the row
+      // level 1 updates in this step
+      T nxt[3], om[3];
+      {
+        const int64_t e0 = (int64_t)irow * nx;
+        nxt[0] = cur[e0];
+        nxt[1] = cur[e0 + F1];
+        nxt[2] = cur[e0 + F2];
+        if (!first) {
+          const int64_t e1 = (int64_t)wrap_sub(irow, S, ny) * nx;
+          om[0] = old[e1];
+          om[1] = old[e1 + F1];
+          om[2] = old[e1 + F2];
+        } else {
+          om[0] = om[1] = om[2] = T(0);
+        }
+      }
+      if constexpr (!SKEW1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) W[0][u][q] = nxt[q];
+      }
+#pragma unroll
+      for (int ee = 1; ee <= G; ++ee) {
+        const int e = SKEW1 ? G + 1 - ee : ee;       // level evaluated now
+        if (e > g) continue;
+        const int c = ((u - e * S) % P + P) % P;     // slot of row i - e S
+        const T(&In)[P][3] = W[e - 1];
+        T syp, syv;
+        {
+          const int up = (c + 1) % P, dn = (c - 1 + P) % P;
+          syp = Fd<ORDER>::template w<T>(0) * (In[up][0] - In[dn][0]);
+          syv = Fd<ORDER>::template w<T>(0) * (In[up][2] - In[dn][2]);
+        }
+#pragma unroll
+        for (int kk = 1; kk < R; ++kk) {
+          const int up = (c + kk + 1) % P, dn = (c - kk - 1 + 2 * P) % P;
+          syp += Fd<ORDER>::template w<T>(kk) * (In[up][0] - In[dn][0]);
+          syv += Fd<ORDER>::template w<T>(kk) * (In[up][2] - In[dn][2]);
+        }
+        const T sxp = lane_dsum<T, ORDER>(In[c][0]);
+        const T sxv = lane_dsum<T, ORDER>(In[c][1]);
+        int row = 0;
+        if (varc || srcs || e == g) row = wrap_sub(irow, e * S, ny);
+        const int64_t pt = (int64_t)row * nx + gx;
+        const T c2 = varc ? a.c2f[pt] : a.c2c;
+        const T dvx = a.invx * sxv;
+        const T dvy = a.invy * syv;
+        T f[3];
+        f[0] = -(c2 * (dvx + dvy));
+        f[1] = -(a.invx * sxp);
+        f[2] = -(a.invy * syp);
+        if (srcs) f[0] += source_term<T>(a.src, a.g.nsrc, blockIdx.z, pt, d.amp[e - 1]);
+        T nw[3];
+        if (e == 1) {
+          if (first) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) nw[q] = In[c][q] + d.h * f[q];        // forward Euler
+          } else {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) nw[q] = om[q] + fac_lf * f[q];         // leap-frog
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) nw[q] = W[e >= 2 ? e - 2 : 0][c][q] + fac_lf * f[q];
+        }
+        if (e == g) {
+          // the pass's last level, at row i - g S
+          const int yo = i0 + k - e * S;
+          if (lane_ok && yo >= ya && yo < yb) {
+            const int64_t eo = rhs_base + pt;
+            if (!final_) {
+#pragma unroll
+              for (int q = 0; q < 3; ++q) {
+                d.out_a[eo + q * F1] = In[c][q];
+                d.out_b[eo + q * F1] = nw[q];
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < 3; ++q) {
+                const T ym1 = (e >= 2) ? W[e >= 2 ? e - 2 : 0][c][q] : (first ? In[c][q] : om[q]);
+                d.ystar[eo + q * F1] =
+                    0.25 * (((double)ym1 + 2.0 * (double)In[c][q]) + (double)nw[q]);
+              }
+            }
+          }
+        } else if (e < G) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) W[e][c][q] = nw[q];
+        }
+      }
+      if constexpr (SKEW1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) W[0][u][q] = nxt[q];
+      }
+      irow = irow + 1 == ny ? 0 : irow + 1;
+    }
+  }
+}
+
+// y_out = sum_j c_j y*_j, j in ascending N, accumulated in FP64.
+template <typename T>
+struct CombineArgs {
+  const double* ystar[GBS_MAX_SEQ];
+  double c[GBS_MAX_SEQ];
+  T* yout;
+  int64_t n;
+  int32_t k;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void combine_kernel(const CombineArgs<T> a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  double v = a.c[0] * a.ystar[0][i];
+  for (int j = 1; j < a.k; ++j) v = v + a.c[j] * a.ystar[j][i];
+  a.yout[i] = (T)v;
+}
+
+}  // namespace gbs

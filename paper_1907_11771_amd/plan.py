@@ -84,6 +84,14 @@ class GBSPlan:
                                              B._arr(ctypes.c_double, weight), float(f0),
                                              float(delay)))
 
+    def set_variant(self, variant):
+        B.check(B.lib().gbs_plan_set_variant(self.handle, int(variant)))
+
+    def variant(self):
+        out = ctypes.c_int32()
+        B.check(B.lib().gbs_plan_get_variant(self.handle, ctypes.byref(out)))
+        return out.value
+
     def set_timing(self, on):
         """on: bool, or the number of macro steps to create events for."""
         B.check(B.lib().gbs_plan_set_timing(self.handle, int(on)))
@@ -95,6 +103,15 @@ class GBSPlan:
         c, d = ctypes.c_double(), ctypes.c_int64()
         B.check(B.lib().gbs_plan_get_timing(self.handle, ctypes.byref(a), ctypes.byref(b),
                                             ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def algorithmic_bytes(self):
+        """(stepping-kernel bytes, launches, auxiliary bytes, launches) per
+        macro step, for the variant in use."""
+        a, b = ctypes.c_double(), ctypes.c_int64()
+        c, d = ctypes.c_double(), ctypes.c_int64()
+        B.check(B.lib().gbs_plan_algorithmic_bytes(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                                   ctypes.byref(c), ctypes.byref(d)))
         return a.value, b.value, c.value, d.value
 
     def updates_per_macro_step(self):

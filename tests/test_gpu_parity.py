@@ -115,6 +115,66 @@ def test_in_place_and_repeatable():
     assert torch.equal(z, y0)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_kernel_variants_agree_bitwise(dtype):
+    # every leap-frog variant computes the same values in the same order
+    ny, nx = 200, 136                   # ragged in both directions
+    sch = schemes.ORDER8_K6
+    cs = fields.lognormal_speed((ny, nx), seed=2)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(nx, ny), 2,
+                           workloads.SIGMA_FD4)
+    y0 = to_dev(np.random.default_rng(3).standard_normal((2, 3, ny, nx)), dtype)
+    outs = []
+    for v in (B.VARIANT_FLAT, B.VARIANT_MARCH8, B.VARIANT_MARCH16, B.VARIANT_MARCH8_NT,
+              B.VARIANT_MARCH16_NT):
+        plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, n_rhs=2, dtype=dtype,
+                        c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
+        plan.set_variant(v)
+        outs.append(plan.step(y0, n_macro=3))
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("variant,band", [(B.VARIANT_TEMPORAL, 128), (B.VARIANT_TEMPORAL, 7),
+                                          (B.VARIANT_TEMPORAL4, 50), (B.VARIANT_TEMPORAL, 1000),
+                                          (B.VARIANT_TEMPORAL_S5, 64), (B.VARIANT_TEMPORAL_S6, 33)])
+def test_temporal_passes_match_streaming(dtype, variant, band):
+    # temporally blocked passes against the streaming sweeps: same values up
+    # to the contraction of products (and FP32 rounding of the levels)
+    ny, nx = 200, 136
+    sch = schemes.ORDER8_K6
+    cs = fields.lognormal_speed((ny, nx), seed=2)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(nx, ny), 2,
+                           workloads.SIGMA_FD4)
+    y0 = to_dev(np.random.default_rng(3).standard_normal((2, 3, ny, nx)), dtype)
+    s = fields.ricker_source_2d(max(nx, ny), cells_per_wavelength=8.0)
+    res = []
+    for v in (B.VARIANT_FLAT, variant):
+        plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, n_rhs=2, dtype=dtype,
+                        c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
+        plan.set_sources([1], [77 * nx + 50], [s["weight"] * 1e-4], s["f0"], s["delay"])
+        plan.set_variant(v)
+        if v != B.VARIANT_FLAT:
+            B.check(B.lib().gbs_plan_set_band(plan.handle, band))
+        res.append(plan.step(y0, t0=0.3 * s["delay"], n_macro=3).cpu().numpy())
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    assert rel_err(res[1], res[0]) <= tol
+
+
+def test_temporal_fd8_matches_oracle():
+    ny, nx = 48, 70
+    sch = schemes.ORDER8_K6
+    steps, c = oracle_weights(sch)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, 1.0, 1.0 / nx, 2, workloads.SIGMA_FD8)
+    y0 = np.random.default_rng(4).standard_normal((3, ny, nx))
+    plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, fd_order=8, check_stability=False)
+    plan.set_variant(B.VARIANT_TEMPORAL)
+    got = plan.step(to_dev(y0[None]), n_macro=3).cpu().numpy()[0]
+    want = G.integrate(OP.Acoustic((ny, nx), c2=1.0, r=4), 0.0, y0, H, 3, steps, c)
+    assert rel_err(got, want) <= TOL64
+
+
 def test_fp32_stepping_error_vs_fp64():
     # FP32 levels, FP64 averaging and combination.  Stated bound for 20
     # macro steps on a 128^2 grid: max rel error <= 2e-5 (measured ~ 2-5e-6;

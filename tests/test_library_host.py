@@ -84,7 +84,7 @@ def test_workspace_bytes_formula():
     steps, w = _cfg2()
     nb = _plan(B.ACOUSTIC2D, (64, 32), 8, steps, w, 1e-3)
     pts = 64 * 32 * 3
-    assert nb == pts * 8 + 2 * 6 * pts * 8
+    assert nb == pts * 8 + 4 * 6 * pts * 8      # acc + two pairs of levels per sequence
 
 
 def test_plan_stability_limit_is_sharp():
@@ -134,3 +134,28 @@ def test_plan_rejects_small_or_misaligned_workspace():
     with pytest.raises(B.GBSError) as e:
         B.plan_create(pr, sc, 1e-4, FAKE_WS + 8, nb)
     assert e.value.status == B.GBS_EINVAL
+
+
+def test_algorithmic_bytes_of_both_schedules():
+    steps, w = _cfg2()
+    pr = B.make_problem(B.ACOUSTIC2D, (64, 32))
+    sc = B.make_scheme(8, steps, w)
+    nb = B.workspace_bytes(pr, sc)
+    h = B.plan_create(pr, sc, 1e-4, FAKE_WS, nb)
+    try:
+        out = [ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()]
+        B.check(B.lib().gbs_plan_algorithmic_bytes(h, *[ctypes.byref(x) for x in out]))
+        pts = 64 * 32
+        # default (temporally blocked, at most 7 evaluations per pass): N = 2, 4, 6 take
+        # one pass (read y0, write y*), N = 8, 10, 12 two (y0 -> 2 levels -> y*)
+        assert out[0].value == pts * (3 * (24 + 24) + 3 * (24 + 48 + 48 + 24))
+        assert out[1].value == 2
+        assert out[2].value == pts * (6 * 24 + 24)              # combine
+        B.check(B.lib().gbs_plan_set_variant(h, B.VARIANT_FLAT))
+        B.check(B.lib().gbs_plan_algorithmic_bytes(h, *[ctypes.byref(x) for x in out]))
+        # streaming: 72 B per stored leap-frog level, last steps 48 B + accumulator
+        want = sum((n - 1) * 72 for n in steps) + 48 * 6 + 24 + 4 * 48 + 48
+        assert out[0].value == pts * want and out[1].value == 12
+        assert out[2].value == pts * 7 * 24                     # first evaluation
+    finally:
+        B.plan_destroy(h)
