@@ -19,6 +19,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 STREAM_BYTES_PER_UPDATE = 72.0   # FP64 2-D acoustic leap-frog update, streaming: 3 F b
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
+# the plain-copy calibration) for the kernel as it is now; see profiles/.  An
+# entry must be removed when its kernel changes.
+MEASURED_TRAFFIC_BYTES_PER_LAUNCH = {
+    "gbs::pass2d<double, 4, 7, false>": 1.607e9,   # profiles/pass2d_acoustic2d_2048_fd4_f64.txt
+}
 
 
 def kernel_names(variant, B):
@@ -126,6 +132,9 @@ def main():
     sb, sl, ab, al = plan.algorithmic_bytes()
     step_bytes = sb * args.steps
     achieved = step_bytes / (step_ms * 1e-3) / 1e9
+    launch_s = step_ms * 1e-3 / max(step_n, 1)
+    measured = MEASURED_TRAFFIC_BYTES_PER_LAUNCH.get(kstep)
+    traffic = measured / launch_s / 1e9 if measured else None
     rec = dict(
         metric="grid-pt RHS updates/s",
         value=upd / dt,
@@ -138,7 +147,8 @@ def main():
                     scheme_order=8, sequences=steps, evals_per_macro_step=1 + sum(steps),
                     H=cfg["H"], macro_steps_timed=args.steps, kernel_variant=variant),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=None, kernel=kstep,
+                      frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                      traffic_bytes_per_launch=measured, kernel=kstep,
                       avg_launch_us=step_ms * 1e3 / max(step_n, 1), launches=step_n,
                       algorithmic_bytes_per_launch=step_bytes / max(step_n, 1)),
         # the streaming form must move 72 B per update; this is the rate those
