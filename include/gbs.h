@@ -122,8 +122,9 @@ int gbs_weights(int32_t p, int32_t m, const int32_t* steps, int32_t n_free,
 int gbs_isb(int32_t k, const int32_t* steps, const double* weights, double* isb_out);
 
 /*
- * gbs_plan_workspace_bytes — device workspace needed by a plan: one FP64
- * accumulator state plus, per sequence, two levels in the plan's dtype
+ * gbs_plan_workspace_bytes — device workspace needed by a plan: a 512-byte
+ * source table, one FP64 accumulator state plus, per sequence, two levels
+ * in the plan's dtype
  * (four for GBS_ACOUSTIC2D, whose temporally blocked passes read one pair
  * and write the other), each 256-byte aligned.
  */
@@ -152,6 +153,8 @@ int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gbs_scheme* s
  * evaluated on the host in FP64 at every substep time t_0 + n h_j.
  *   n_src <= GBS_MAX_SRC (0 removes the sources); arrays host [n_src];
  *   flat_index is the index within one field ([Z][Y][X], x fastest).
+ *   The table is copied into the workspace; the call synchronises the
+ *   plan's stream.
  */
 int gbs_plan_set_sources(gbs_plan* plan, int32_t n_src, const int32_t* rhs,
                          const int64_t* flat_index, const double* weight, double f0,
@@ -233,6 +236,47 @@ int gbs_plan_algorithmic_bytes(const gbs_plan* plan, double* step_bytes, int64_t
 int gbs_plan_updates_per_macro_step(const gbs_plan* plan, double* updates);
 
 int gbs_plan_destroy(gbs_plan* plan);
+
+/*
+ * Batches of independent 2-D acoustic instances (GBS_ACOUSTIC2D, n_rhs = 1,
+ * no sources), each with its own grid size, coefficient (constant c^2 or a
+ * c^2 field) and macro step H[i], one common scheme, dtype and stencil
+ * order.  The instances' sequences (Sect. 3.2) are advanced by the
+ * temporally blocked passes: one launch per pass round covers every
+ * (instance, sequence) pair, one more launch forms every instance's
+ * combination; the per-launch work lists live in the workspace.
+ *
+ * gbs_batch_workspace_bytes — workspace for the item tables plus four
+ *   levels per (instance, sequence).
+ * gbs_batch_plan_create — validates every instance as gbs_plan_create does
+ *   (stability check per instance with its own H and c_max); probs and H are
+ *   host arrays [n_inst], copied; workspace as for gbs_plan_create.
+ * gbs_batch_step — n_macro macro steps of every instance, in place: y is a
+ *   host array [n_inst] of device state pointers ([1][3][ny][nx] each).
+ *   The item tables are rebuilt and uploaded (synchronising the plan's
+ *   stream) when the pointers differ from the previous call.
+ * gbs_batch_set_variant — kernel variant (GBS_VARIANT_TEMPORAL*, 0 keeps
+ *   the current one) and rows per band (0 keeps the current one).
+ * gbs_batch_set_graph — enabled != 0: one macro step is captured once in a
+ *   hipGraph on a stream the plan owns and replayed n_macro times, ordered
+ *   after and before the caller's stream by events.
+ * gbs_batch_autotune — times every candidate variant and band on the given
+ *   states (which are advanced: pass copies) and keeps the fastest;
+ *   variant_out and band_out are nullable.
+ */
+typedef struct gbs_batch_plan gbs_batch_plan;
+int gbs_batch_workspace_bytes(int32_t n_inst, const gbs_problem* probs, const gbs_scheme* sch,
+                              size_t* bytes);
+int gbs_batch_plan_create(gbs_batch_plan** out, int32_t n_inst, const gbs_problem* probs,
+                          const gbs_scheme* sch, const double* H, void* workspace,
+                          size_t workspace_bytes, void* hip_stream);
+int gbs_batch_set_variant(gbs_batch_plan* plan, int32_t variant, int32_t band);
+int gbs_batch_set_graph(gbs_batch_plan* plan, int32_t enabled);
+int gbs_batch_step(gbs_batch_plan* plan, int32_t n_macro, void* const* y);
+int gbs_batch_autotune(gbs_batch_plan* plan, void* const* y, int32_t macro_steps,
+                       int32_t* variant_out, int32_t* band_out);
+int gbs_batch_updates_per_macro_step(const gbs_batch_plan* plan, double* updates);
+int gbs_batch_plan_destroy(gbs_batch_plan* plan);
 
 /* Message for the last non-zero status returned on this thread. */
 const char* gbs_last_error(void);

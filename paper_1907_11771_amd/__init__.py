@@ -9,4 +9,4 @@ the modules here only marshal arguments to its C ABI (include/gbs.h).
 """
 from .binding import (ACOUSTIC2D, ACOUSTIC3D, ADVECT1D, F32, F64, GBSError, isb,  # noqa: F401
                       weights)
-from .plan import GBSPlan, scheme_weights  # noqa: F401
+from .plan import GBSBatch, GBSPlan, scheme_weights  # noqa: F401

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -61,9 +62,10 @@ struct gbs_plan {
   hipStream_t stream = nullptr;
   double* acc = nullptr;
   void* lev[GBS_MAX_SEQ][2];
-  // sources
+  // sources (host copy, and a device copy at the start of the workspace)
   int nsrc = 0;
   SrcDesc src[GBS_MAX_SRC];
+  SrcDesc* src_dev = nullptr;
   double f0 = 0, delay = 0;
   // leap-frog kernel variant (GBS_VARIANT_*) and rows per band of the
   // temporally blocked passes
@@ -146,10 +148,32 @@ int validate_scheme(const gbs_scheme* s) {
 // write the other (and the FP64 y* into a free pair at the end)
 int levels_per_seq(const gbs_problem* p) { return p->op == GBS_ACOUSTIC2D ? 4 : 2; }
 
+constexpr size_t kSrcBytes = (GBS_MAX_SRC * sizeof(SrcDesc) + kAlign - 1) / kAlign * kAlign;
+
 size_t workspace_bytes(const gbs_problem* p, int k) {
   const int64_t pts = p->n[0] * p->n[1] * p->n[2];
   const size_t elems = (size_t)p->n_rhs * fields_of(p->op) * pts;
-  return align_up(elems * 8) + levels_per_seq(p) * (size_t)k * align_up(elems * dsize(p->dtype));
+  return kSrcBytes + align_up(elems * 8) +
+         levels_per_seq(p) * (size_t)k * align_up(elems * dsize(p->dtype));
+}
+
+// App. A: the operator's eigenvalues (on the imaginary axis, modulus up to
+// rho = c_max sigma sqrt(sum_a n_a^2)) must lie in the stability domain.
+int check_stable(const gbs_problem* prob, const gbs_scheme* sch, double H) {
+  if (prob->flags & GBS_FLAG_NO_STABILITY_CHECK) return GBS_OK;
+  std::vector<Rational> c(sch->k);
+  for (int j = 0; j < sch->k; ++j) c[j] = Rational::from_double(sch->weights[j]);
+  const double isb = isb_of(sch->k, sch->steps, c);
+  const int d = dims_of(prob->op);
+  double s2 = 0;
+  for (int a = 0; a < d; ++a) s2 += (double)prob->n[a] * (double)prob->n[a];
+  const double cmax = prob->op == GBS_ADVECT1D
+                          ? 1.0
+                          : (prob->c2_field ? prob->c_max : std::sqrt(prob->c2));
+  const double rho = cmax * stencil_sigma(prob->fd_order) * std::sqrt(s2);
+  if (H * rho > isb)
+    return fail(GBS_EUNSTABLE, "H * rho = %.6g exceeds the scheme's ISB %.6g", H * rho, isb);
+  return GBS_OK;
 }
 
 double ricker(double t, double f0, double delay) {
@@ -211,7 +235,7 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   T c2c, invz;
   fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
   pa.c2c = c2c;
-  std::memcpy(pa.src, P->src, sizeof(P->src));
+  pa.src_dev = P->src_dev;
   pa.band = P->band;
   pa.nbands = (int)((P->prob.n[1] + P->band - 1) / P->band);
   const int nx = (int)P->prob.n[0];
@@ -416,20 +440,8 @@ extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gb
     const size_t need = workspace_bytes(prob, sch->k);
     if (ws_bytes < need)
       return fail(GBS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-    if (!(prob->flags & GBS_FLAG_NO_STABILITY_CHECK)) {
-      std::vector<Rational> c(sch->k);
-      for (int j = 0; j < sch->k; ++j) c[j] = Rational::from_double(sch->weights[j]);
-      const double isb = isb_of(sch->k, sch->steps, c);
-      const int d = dims_of(prob->op);
-      double s2 = 0;
-      for (int a = 0; a < d; ++a) s2 += (double)prob->n[a] * (double)prob->n[a];
-      const double cmax = prob->op == GBS_ADVECT1D
-                              ? 1.0
-                              : (prob->c2_field ? prob->c_max : std::sqrt(prob->c2));
-      const double rho = cmax * stencil_sigma(prob->fd_order) * std::sqrt(s2);
-      if (H * rho > isb)
-        return fail(GBS_EUNSTABLE, "H * rho = %.6g exceeds the scheme's ISB %.6g", H * rho, isb);
-    }
+    st = check_stable(prob, sch, H);
+    if (st) return st;
     gbs_plan* P = new gbs_plan();
     P->prob = *prob;
     P->k = sch->k;
@@ -447,6 +459,8 @@ extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gb
     P->stream = (hipStream_t)hip_stream;
     const size_t elems = (size_t)prob->n_rhs * P->state;
     char* base = (char*)workspace;
+    P->src_dev = (SrcDesc*)base;
+    base += kSrcBytes;
     P->acc = (double*)base;
     base += align_up(elems * 8);
     const size_t lb = align_up(elems * dsize(prob->dtype));
@@ -485,6 +499,10 @@ extern "C" int gbs_plan_set_sources(gbs_plan* P, int32_t n_src, const int32_t* r
     P->src[s].w = weight[s];
     P->src[s].rhs = rhs[s];
   }
+  if (hipMemcpyAsync(P->src_dev, P->src, sizeof(P->src), hipMemcpyHostToDevice, P->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(P->stream) != hipSuccess)
+    return fail(GBS_EDEVICE, "copying the sources to the workspace failed");
   P->nsrc = n_src;
   P->f0 = f0;
   P->delay = delay;
@@ -633,3 +651,412 @@ extern "C" int gbs_plan_destroy(gbs_plan* P) {
 }
 
 extern "C" const char* gbs_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Batches: many independent 2-D acoustic instances (own grid size, c^2 and H)
+// advanced together.  Every pass round of every (instance, sequence) pair is
+// one launch over a device-side item table; the combination of all
+// instances is one more launch.  A macro step can be captured once in a
+// hipGraph and replayed.
+// ---------------------------------------------------------------------------
+
+struct gbs_batch_plan {
+  int n = 0, k = 0, dtype = GBS_F64, fd_order = 4;
+  std::vector<gbs_problem> prob;
+  std::vector<double> H;
+  int32_t steps[GBS_MAX_SEQ];
+  double w[GBS_MAX_SEQ];
+  int order[GBS_MAX_SEQ];
+  int variant = GBS_VARIANT_TEMPORAL;
+  int band = 64;
+  hipStream_t stream = nullptr;   // caller's stream
+  hipStream_t gstream = nullptr;  // own stream for graph capture and replay
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // device tables (in the workspace) and their host images
+  char* tab_dev = nullptr;
+  size_t tab_bytes = 0;
+  std::vector<char> tab_host;
+  std::vector<size_t> round_off;   // byte offset of each round's item table
+  std::vector<int> round_items, round_waves;
+  size_t comb_off = 0;
+  int comb_blocks = 0;
+  std::vector<void*> ycache;       // state pointers the tables were built for
+  std::vector<std::vector<std::array<std::array<void*, 2>, 2>>> pair;  // [inst][seq][pair][level]
+  bool use_graph = false;
+  hipGraphExec_t graph = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+int batch_gmax(int variant, int fd_order) {
+  if (fd_order == 8) return 3;
+  switch (variant) {
+    case GBS_VARIANT_TEMPORAL4: return 4;
+    case GBS_VARIANT_TEMPORAL_S5: return 5;
+    case GBS_VARIANT_TEMPORAL_S6: return 6;
+    default: return 7;
+  }
+}
+
+size_t batch_level_bytes(const gbs_problem& p) {
+  return align_up((size_t)3 * p.n[0] * p.n[1] * dsize(p.dtype));
+}
+
+// upper bound of the item tables: every (instance, sequence) pair in every
+// round (at most N_max + 1 rounds) plus one combine item per instance
+size_t batch_table_bytes(int n, int k, int nmax) {
+  const size_t item = std::max(sizeof(PassItem<double>), sizeof(PassItem<float>));
+  const size_t comb = std::max(sizeof(CombineItem<double>), sizeof(CombineItem<float>));
+  return align_up((size_t)(nmax + 1) * n * k * item) + (size_t)(nmax + 1) * kAlign +
+         align_up((size_t)n * comb);
+}
+
+template <typename T>
+void batch_build_tables(gbs_batch_plan* B, void* const* y) {
+  const int G = batch_gmax(B->variant, B->fd_order);
+  const int R = B->fd_order / 2;
+  int npass[GBS_MAX_SEQ], gsz[GBS_MAX_SEQ][32], maxpass = 0;
+  for (int j = 0; j < B->k; ++j) {
+    const int E = B->steps[j] + 1, np = (E + G - 1) / G;
+    npass[j] = np;
+    for (int q = 0; q < np; ++q) gsz[j][q] = E / np + (q < E % np ? 1 : 0);
+    maxpass = std::max(maxpass, np);
+  }
+  B->tab_host.assign(B->tab_bytes, 0);
+  B->round_off.assign(maxpass, 0);
+  B->round_items.assign(maxpass, 0);
+  B->round_waves.assign(maxpass, 0);
+  size_t off = 0;
+  for (int q = 0; q < maxpass; ++q) {
+    B->round_off[q] = off;
+    PassItem<T>* items = (PassItem<T>*)(B->tab_host.data() + off);
+    int m = 0, waves = 0;
+    for (int i = 0; i < B->n; ++i) {
+      const gbs_problem& p = B->prob[i];
+      const int nx = (int)p.n[0], ny = (int)p.n[1];
+      for (int r = 0; r < B->k; ++r) {
+        const int j = B->order[r];
+        if (q >= npass[j]) continue;
+        PassItem<T>& it = items[m++];
+        auto& pr = B->pair[i][j];
+        it.cur = q == 0 ? (const T*)y[i] : (const T*)pr[(q - 1) % 2][1];
+        it.old = q == 0 ? nullptr : (const T*)pr[(q - 1) % 2][0];
+        it.out_a = (T*)pr[q % 2][0];
+        it.out_b = (T*)pr[q % 2][1];
+        it.ystar = (double*)pr[q % 2][0];
+        it.c2f = (const T*)p.c2_field;
+        it.field = (int64_t)nx * ny;
+        it.h = (T)(B->H[i] / B->steps[j]);
+        it.c2c = (T)p.c2;
+        const double den = B->fd_order == 8 ? 840.0 : 12.0;
+        it.invx = (T)((double)nx / den);
+        it.invy = (T)((double)ny / den);
+        it.nx = nx;
+        it.ny = ny;
+        it.g = gsz[j][q];
+        it.flags = (q == 0 ? PASS_FIRST : 0) | (q == npass[j] - 1 ? PASS_FINAL : 0);
+        const int wv = 64 - 2 * it.g * R;
+        it.strips = (nx + wv - 1) / wv;
+        it.nbands = (ny + B->band - 1) / B->band;
+        it.band = B->band;
+        it.wave_begin = waves;
+        waves += it.strips * it.nbands;
+      }
+    }
+    B->round_items[q] = m;
+    B->round_waves[q] = waves;
+    off += align_up((size_t)m * sizeof(PassItem<T>));
+  }
+  B->comb_off = off;
+  CombineItem<T>* ci = (CombineItem<T>*)(B->tab_host.data() + off);
+  int blocks = 0;
+  for (int i = 0; i < B->n; ++i) {
+    const gbs_problem& p = B->prob[i];
+    CombineItem<T>& c = ci[i];
+    c.k = B->k;
+    c.n = (int64_t)3 * p.n[0] * p.n[1];
+    c.yout = (T*)y[i];
+    for (int r = 0; r < B->k; ++r) {
+      const int j = B->order[r];
+      c.c[r] = B->w[j];
+      c.ystar[r] = (const double*)B->pair[i][j][(npass[j] - 1) % 2][0];
+    }
+    c.block_begin = blocks;
+    blocks += (int)((c.n + 255) / 256);
+  }
+  B->comb_blocks = blocks;
+}
+
+template <typename T>
+void batch_launch_macro_step(gbs_batch_plan* B, hipStream_t s) {
+  const int G = batch_gmax(B->variant, B->fd_order);
+  for (size_t q = 0; q < B->round_off.size(); ++q) {
+    BatchPassArgs<T> a;
+    a.items = (const PassItem<T>*)(B->tab_dev + B->round_off[q]);
+    a.n_items = B->round_items[q];
+    a.total_waves = B->round_waves[q];
+    const dim3 grid((unsigned)((a.total_waves + 3) / 4));
+    if (B->fd_order == 8) {
+      hipLaunchKernelGGL((pass2d_batch<T, 8, 3, true>), grid, dim3(256), 0, s, a);
+    } else if (G == 4) {
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 4, false>), grid, dim3(256), 0, s, a);
+    } else if (G == 5) {
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 5, true>), grid, dim3(256), 0, s, a);
+    } else if (G == 6) {
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 6, true>), grid, dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 7, false>), grid, dim3(256), 0, s, a);
+    }
+  }
+  hipLaunchKernelGGL((combine_batch<T>), dim3((unsigned)B->comb_blocks), dim3(256), 0, s,
+                     (const CombineItem<T>*)(B->tab_dev + B->comb_off), B->n, B->comb_blocks);
+}
+
+void batch_drop_graph(gbs_batch_plan* B) {
+  if (B->graph) {
+    hipGraphExecDestroy(B->graph);
+    B->graph = nullptr;
+  }
+}
+
+// (Re)build and upload the item tables when the state pointers change.
+int batch_prepare(gbs_batch_plan* B, void* const* y) {
+  bool same = (int)B->ycache.size() == B->n;
+  for (int i = 0; same && i < B->n; ++i) same = B->ycache[i] == y[i];
+  if (same && !B->tab_host.empty()) return GBS_OK;
+  if (hipStreamSynchronize(B->stream) != hipSuccess) return fail(GBS_EDEVICE, "stream sync failed");
+  if (B->gstream && hipStreamSynchronize(B->gstream) != hipSuccess)
+    return fail(GBS_EDEVICE, "stream sync failed");
+  if (B->dtype == GBS_F64) batch_build_tables<double>(B, y);
+  else batch_build_tables<float>(B, y);
+  if (hipMemcpy(B->tab_dev, B->tab_host.data(), B->tab_bytes, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(GBS_EDEVICE, "uploading the batch tables failed");
+  B->ycache.assign(y, y + B->n);
+  batch_drop_graph(B);
+  return GBS_OK;
+}
+
+int batch_run(gbs_batch_plan* B, int n_macro) {
+  if (!B->use_graph) {
+    for (int m = 0; m < n_macro; ++m) {
+      if (B->dtype == GBS_F64) batch_launch_macro_step<double>(B, B->stream);
+      else batch_launch_macro_step<float>(B, B->stream);
+    }
+  } else {
+    if (!B->gstream && hipStreamCreateWithFlags(&B->gstream, hipStreamNonBlocking) != hipSuccess)
+      return fail(GBS_EDEVICE, "creating the graph stream failed");
+    if (!B->ev_in && (hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
+                      hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess))
+      return fail(GBS_EDEVICE, "creating events failed");
+    if (!B->graph) {
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(B->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(GBS_EDEVICE, "graph capture failed to start");
+      if (B->dtype == GBS_F64) batch_launch_macro_step<double>(B, B->gstream);
+      else batch_launch_macro_step<float>(B, B->gstream);
+      if (hipStreamEndCapture(B->gstream, &g) != hipSuccess)
+        return fail(GBS_EDEVICE, "graph capture failed");
+      const hipError_t e = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(GBS_EDEVICE, "graph instantiation failed");
+    }
+    // order the replays after the caller's stream and the caller's stream after them
+    hipEventRecord(B->ev_in, B->stream);
+    hipStreamWaitEvent(B->gstream, B->ev_in, 0);
+    for (int m = 0; m < n_macro; ++m)
+      if (hipGraphLaunch(B->graph, B->gstream) != hipSuccess)
+        return fail(GBS_EDEVICE, "graph launch failed");
+    hipEventRecord(B->ev_out, B->gstream);
+    hipStreamWaitEvent(B->stream, B->ev_out, 0);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GBS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return GBS_OK;
+}
+
+int batch_validate(int n_inst, const gbs_problem* probs, const gbs_scheme* sch, const double* H) {
+  if (n_inst < 1 || !probs || !H) return fail(GBS_EINVAL, "batch: empty or null arguments");
+  int st = validate_scheme(sch);
+  if (st) return st;
+  for (int i = 0; i < n_inst; ++i) {
+    st = validate_problem(&probs[i]);
+    if (st) return st;
+    if (probs[i].op != GBS_ACOUSTIC2D || probs[i].n_rhs != 1)
+      return fail(GBS_EUNSUPPORTED, "batch instance %d: only 2-D acoustic, one right-hand side", i);
+    if (probs[i].dtype != probs[0].dtype || probs[i].fd_order != probs[0].fd_order)
+      return fail(GBS_EINVAL, "batch instance %d: dtype and stencil order must match", i);
+    if (!(H[i] > 0) || !std::isfinite(H[i])) return fail(GBS_EINVAL, "batch instance %d: bad H", i);
+    st = check_stable(&probs[i], sch, H[i]);
+    if (st) return fail(st, "batch instance %d: %s", i, gbs_last_error());
+  }
+  return GBS_OK;
+}
+
+size_t batch_bytes(int n_inst, const gbs_problem* probs, const gbs_scheme* sch) {
+  int nmax = 0;
+  for (int j = 0; j < sch->k; ++j) nmax = std::max(nmax, (int)sch->steps[j]);
+  size_t b = batch_table_bytes(n_inst, sch->k, nmax);
+  for (int i = 0; i < n_inst; ++i) b += 4 * (size_t)sch->k * batch_level_bytes(probs[i]);
+  return b;
+}
+
+}  // namespace
+
+extern "C" int gbs_batch_workspace_bytes(int32_t n_inst, const gbs_problem* probs,
+                                         const gbs_scheme* sch, size_t* bytes) {
+  if (!bytes) return fail(GBS_EINVAL, "bytes is null");
+  if (n_inst < 1 || !probs) return fail(GBS_EINVAL, "batch: empty or null arguments");
+  int st = validate_scheme(sch);
+  if (st) return st;
+  for (int i = 0; i < n_inst; ++i) {
+    st = validate_problem(&probs[i]);
+    if (st) return st;
+  }
+  *bytes = batch_bytes(n_inst, probs, sch);
+  return GBS_OK;
+}
+
+extern "C" int gbs_batch_plan_create(gbs_batch_plan** out, int32_t n_inst, const gbs_problem* probs,
+                                     const gbs_scheme* sch, const double* H, void* workspace,
+                                     size_t ws_bytes, void* hip_stream) {
+  try {
+    if (!out) return fail(GBS_EINVAL, "out is null");
+    *out = nullptr;
+    int st = batch_validate(n_inst, probs, sch, H);
+    if (st) return st;
+    if (!workspace || (uintptr_t)workspace % kAlign)
+      return fail(GBS_EINVAL, "workspace must be non-null and 256-byte aligned");
+    const size_t need = batch_bytes(n_inst, probs, sch);
+    if (ws_bytes < need) return fail(GBS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    gbs_batch_plan* B = new gbs_batch_plan();
+    B->n = n_inst;
+    B->k = sch->k;
+    B->dtype = probs[0].dtype;
+    B->fd_order = probs[0].fd_order;
+    B->prob.assign(probs, probs + n_inst);
+    B->H.assign(H, H + n_inst);
+    int nmax = 0;
+    for (int j = 0; j < sch->k; ++j) {
+      B->steps[j] = sch->steps[j];
+      B->w[j] = sch->weights[j];
+      B->order[j] = j;
+      nmax = std::max(nmax, (int)sch->steps[j]);
+    }
+    std::sort(B->order, B->order + B->k, [&](int a, int b) { return B->steps[a] < B->steps[b]; });
+    B->stream = (hipStream_t)hip_stream;
+    B->ws = (char*)workspace;
+    B->ws_bytes = ws_bytes;
+    B->tab_dev = B->ws;
+    B->tab_bytes = batch_table_bytes(n_inst, sch->k, nmax);
+    char* base = B->ws + B->tab_bytes;
+    B->pair.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      const size_t lb = batch_level_bytes(probs[i]);
+      B->pair[i].resize(sch->k);
+      for (int j = 0; j < sch->k; ++j)
+        for (int q = 0; q < 2; ++q)
+          for (int l = 0; l < 2; ++l) {
+            B->pair[i][j][q][l] = base;
+            base += lb;
+          }
+    }
+    *out = B;
+    return GBS_OK;
+  } catch (const std::exception& e) {
+    return fail(GBS_EINVAL, "gbs_batch_plan_create: %s", e.what());
+  }
+}
+
+extern "C" int gbs_batch_set_variant(gbs_batch_plan* B, int32_t variant, int32_t band) {
+  if (!B) return fail(GBS_EINVAL, "plan is null");
+  if (variant != 0 && !is_temporal(variant))
+    return fail(GBS_EUNSUPPORTED, "batches use the temporally blocked variants");
+  if (band < 0 || band > (1 << 20)) return fail(GBS_EINVAL, "band out of range");
+  if (variant) B->variant = variant;
+  if (band) B->band = band;
+  B->ycache.clear();       // tables and graph are rebuilt on the next step
+  B->tab_host.clear();
+  batch_drop_graph(B);
+  return GBS_OK;
+}
+
+extern "C" int gbs_batch_set_graph(gbs_batch_plan* B, int32_t enabled) {
+  if (!B) return fail(GBS_EINVAL, "plan is null");
+  B->use_graph = enabled != 0;
+  return GBS_OK;
+}
+
+extern "C" int gbs_batch_step(gbs_batch_plan* B, int32_t n_macro, void* const* y) {
+  if (!B || !y) return fail(GBS_EINVAL, "null argument");
+  if (n_macro < 0) return fail(GBS_EINVAL, "n_macro must be >= 0");
+  for (int i = 0; i < B->n; ++i)
+    if (!y[i]) return fail(GBS_EINVAL, "state %d is null", i);
+  if (n_macro == 0) return GBS_OK;
+  int st = batch_prepare(B, y);
+  if (st) return st;
+  return batch_run(B, n_macro);
+}
+
+extern "C" int gbs_batch_autotune(gbs_batch_plan* B, void* const* y, int32_t macro_steps,
+                                  int32_t* variant_out, int32_t* band_out) {
+  if (!B || !y || macro_steps < 1) return fail(GBS_EINVAL, "bad arguments");
+  const int variants[] = {GBS_VARIANT_TEMPORAL, GBS_VARIANT_TEMPORAL4, GBS_VARIANT_TEMPORAL_S5};
+  const int bands[] = {32, 64, 128};
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(GBS_EDEVICE, "creating events failed");
+  const bool graph = B->use_graph;
+  B->use_graph = false;
+  float best = 1e30f;
+  int bv = B->variant, bb = B->band;
+  for (int v : variants) {
+    if (B->fd_order == 8 && v != GBS_VARIANT_TEMPORAL) continue;
+    for (int band : bands) {
+      gbs_batch_set_variant(B, v, band);
+      int st = gbs_batch_step(B, 1, y);                  // warm-up (and table upload)
+      if (st) { hipEventDestroy(a); hipEventDestroy(b); B->use_graph = graph; return st; }
+      hipEventRecord(a, B->stream);
+      st = gbs_batch_step(B, macro_steps, y);
+      hipEventRecord(b, B->stream);
+      if (st || hipEventSynchronize(b) != hipSuccess) {
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+        B->use_graph = graph;
+        return st ? st : fail(GBS_EDEVICE, "event sync failed");
+      }
+      float ms = 0;
+      hipEventElapsedTime(&ms, a, b);
+      if (ms < best) { best = ms; bv = v; bb = band; }
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  gbs_batch_set_variant(B, bv, bb);
+  B->use_graph = graph;
+  if (variant_out) *variant_out = bv;
+  if (band_out) *band_out = bb;
+  return GBS_OK;
+}
+
+extern "C" int gbs_batch_updates_per_macro_step(const gbs_batch_plan* B, double* updates) {
+  if (!B || !updates) return fail(GBS_EINVAL, "null argument");
+  int evals = 1;
+  for (int j = 0; j < B->k; ++j) evals += B->steps[j];
+  double pts = 0;
+  for (const auto& p : B->prob) pts += (double)p.n[0] * p.n[1];
+  *updates = pts * evals;
+  return GBS_OK;
+}
+
+extern "C" int gbs_batch_plan_destroy(gbs_batch_plan* B) {
+  if (!B) return GBS_OK;
+  if (B->gstream) hipStreamSynchronize(B->gstream);
+  batch_drop_graph(B);
+  if (B->gstream) hipStreamDestroy(B->gstream);
+  if (B->ev_in) hipEventDestroy(B->ev_in);
+  if (B->ev_out) hipEventDestroy(B->ev_out);
+  delete B;
+  return GBS_OK;
+}

@@ -47,7 +47,7 @@ struct PassSeq {
 template <typename T>
 struct PassArgs {
   PassSeq<T> seq[GBS_MAX_SEQ];
-  SrcDesc src[GBS_MAX_SRC];
+  const SrcDesc* src_dev;    // device copy of the point sources
   Geometry g;
   const T* c2f;
   T c2c;
@@ -99,6 +99,23 @@ __device__ __forceinline__ int wrap_sub(int r, int d, int n) {
   return r;
 }
 
+// Everything one wavefront needs for its part of a pass, by value.
+template <typename T>
+struct PassWork {
+  const T* cur;        // later pass: y_s; first pass: y_0   (this right-hand side)
+  const T* old;        // later pass: y_{s-1}
+  T* out_a;            // non-final: A_{g-1}
+  T* out_b;            // non-final: A_g
+  double* ystar;       // final: y* (FP64)
+  const T* c2f;        // coefficient field or null
+  const SrcDesc* src;  // device array of point sources (global memory) or null
+  int64_t field;       // points per field
+  int64_t rhs;         // right-hand-side index (for sources)
+  T h, c2c, invx, invy;
+  int32_t nx, ny, g, flags, band, nsrc;
+  double amp[PASS_GMAX];
+};
+
 // One wavefront's pass over its strip and band.
 //
 // Time skew between consecutive levels: with SKEW1 = false level e is
@@ -110,37 +127,31 @@ __device__ __forceinline__ int wrap_sub(int r, int d, int n) {
 // cost of one more window row per level.  The number of evaluations g of a
 // pass (at most G) is a runtime value, uniform over the wavefront.
 template <typename T, int ORDER, int G, bool SKEW1>
-__global__ __launch_bounds__(256) void pass2d(const PassArgs<T> a) {
+__device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, const int band) {
   constexpr int R = Fd<ORDER>::R;
   constexpr int S = SKEW1 ? R + 1 : R;               // rows between consecutive levels
   constexpr int P = SKEW1 ? 2 * R + 2 : 2 * R + 1;   // window rows per level
-  const PassSeq<T>& d = a.seq[blockIdx.y];
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  const int strip = wave % a.max_strips;
-  const int band = wave / a.max_strips;
-  if (strip >= d.strips || band >= a.nbands) return;
   const int lane = threadIdx.x & 63;
-  const int nx = a.g.nx, ny = a.g.ny;
-  const int g = d.g;
+  const int nx = w.nx, ny = w.ny;
+  const int g = w.g;
   const int halo = g * R;
   const int wv = 64 - 2 * halo;
   const int x0 = strip * wv;
   const int col = x0 - halo + lane;                  // unwrapped column of this lane
   const int gx = pmod(col, nx);
   const bool lane_ok = lane >= halo && lane < 64 - halo && col < nx;
-  const int ya = band * a.band;
-  const int yb = min(ya + a.band, ny);
+  const int ya = band * w.band;
+  const int yb = min(ya + w.band, ny);
   const int i0 = ya - halo;                          // first input row (A_0)
   const int niter = (yb - ya) + halo + g * S;        // until A_g reaches row yb - 1
-  const int64_t rhs_base = (int64_t)blockIdx.z * a.g.state;
-  const int64_t F1 = a.g.field, F2 = 2 * a.g.field;
-  const bool first = d.flags & PASS_FIRST;
-  const bool final_ = d.flags & PASS_FINAL;
-  const bool varc = a.c2f != nullptr;
-  const bool srcs = a.g.nsrc > 0;
-  const T fac_lf = T(2) * d.h;
-  const T* __restrict__ cur = d.cur + rhs_base + gx;
-  const T* __restrict__ old = first ? cur : d.old + rhs_base + gx;
+  const int64_t F1 = w.field, F2 = 2 * w.field;
+  const bool first = w.flags & PASS_FIRST;
+  const bool final_ = w.flags & PASS_FINAL;
+  const bool varc = w.c2f != nullptr;
+  const bool srcs = w.nsrc > 0;
+  const T fac_lf = T(2) * w.h;
+  const T* __restrict__ cur = w.cur + gx;
+  const T* __restrict__ old = first ? cur : w.old + gx;
 
   T W[G][P][3];
 #pragma unroll
@@ -199,19 +210,19 @@ __global__ __launch_bounds__(256) void pass2d(const PassArgs<T> a) {
         int row = 0;
         if (varc || srcs || e == g) row = wrap_sub(irow, e * S, ny);
         const int64_t pt = (int64_t)row * nx + gx;
-        const T c2 = varc ? a.c2f[pt] : a.c2c;
-        const T dvx = a.invx * sxv;
-        const T dvy = a.invy * syv;
+        const T c2 = varc ? w.c2f[pt] : w.c2c;
+        const T dvx = w.invx * sxv;
+        const T dvy = w.invy * syv;
         T f[3];
         f[0] = -(c2 * (dvx + dvy));
-        f[1] = -(a.invx * sxp);
-        f[2] = -(a.invy * syp);
-        if (srcs) f[0] += source_term<T>(a.src, a.g.nsrc, blockIdx.z, pt, d.amp[e - 1]);
+        f[1] = -(w.invx * sxp);
+        f[2] = -(w.invy * syp);
+        if (srcs) f[0] += source_term<T>(w.src, w.nsrc, w.rhs, pt, w.amp[e - 1]);
         T nw[3];
         if (e == 1) {
           if (first) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) nw[q] = In[c][q] + d.h * f[q];        // forward Euler
+            for (int q = 0; q < 3; ++q) nw[q] = In[c][q] + w.h * f[q];        // forward Euler
           } else {
 #pragma unroll
             for (int q = 0; q < 3; ++q) nw[q] = om[q] + fac_lf * f[q];         // leap-frog
@@ -224,18 +235,17 @@ __global__ __launch_bounds__(256) void pass2d(const PassArgs<T> a) {
           // the pass's last level, at row i - g S
           const int yo = i0 + k - e * S;
           if (lane_ok && yo >= ya && yo < yb) {
-            const int64_t eo = rhs_base + pt;
             if (!final_) {
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                d.out_a[eo + q * F1] = In[c][q];
-                d.out_b[eo + q * F1] = nw[q];
+                w.out_a[pt + q * F1] = In[c][q];
+                w.out_b[pt + q * F1] = nw[q];
               }
             } else {
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
                 const T ym1 = (e >= 2) ? W[e >= 2 ? e - 2 : 0][c][q] : (first ? In[c][q] : om[q]);
-                d.ystar[eo + q * F1] =
+                w.ystar[pt + q * F1] =
                     0.25 * (((double)ym1 + 2.0 * (double)In[c][q]) + (double)nw[q]);
               }
             }
@@ -252,6 +262,102 @@ __global__ __launch_bounds__(256) void pass2d(const PassArgs<T> a) {
       irow = irow + 1 == ny ? 0 : irow + 1;
     }
   }
+}
+
+// One problem: blockIdx.y selects the sequence (its descriptor in the kernel
+// arguments), blockIdx.z the right-hand side.
+template <typename T, int ORDER, int G, bool SKEW1>
+__global__ __launch_bounds__(256) void pass2d(const PassArgs<T> a) {
+  const PassSeq<T>& d = a.seq[blockIdx.y];
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int strip = wave % a.max_strips;
+  const int band = wave / a.max_strips;
+  if (strip >= d.strips || band >= a.nbands) return;
+  const int64_t base = (int64_t)blockIdx.z * a.g.state;
+  PassWork<T> w;
+  w.cur = d.cur + base;
+  w.old = d.old ? d.old + base : nullptr;
+  w.out_a = d.out_a + base;
+  w.out_b = d.out_b + base;
+  w.ystar = d.ystar + base;
+  w.c2f = a.c2f;
+  w.src = a.src_dev;
+  w.field = a.g.field;
+  w.rhs = blockIdx.z;
+  w.h = d.h;
+  w.c2c = a.c2c;
+  w.invx = a.invx;
+  w.invy = a.invy;
+  w.nx = a.g.nx;
+  w.ny = a.g.ny;
+  w.g = d.g;
+  w.flags = d.flags;
+  w.band = a.band;
+  w.nsrc = a.g.nsrc;
+#pragma unroll
+  for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = d.amp[e];
+  pass_body<T, ORDER, G, SKEW1>(w, strip, band);
+}
+
+// A batch of problems: the passes of one round of every (instance, sequence)
+// are items of a device table; wave w belongs to the item whose first wave is
+// the largest wave_begin <= w.
+template <typename T>
+struct PassItem {
+  const T* cur;
+  const T* old;
+  T* out_a;
+  T* out_b;
+  double* ystar;
+  const T* c2f;
+  int64_t field;
+  T h, c2c, invx, invy;
+  int32_t nx, ny, g, flags, strips, nbands, band, wave_begin;
+};
+
+template <typename T>
+struct BatchPassArgs {
+  const PassItem<T>* items;
+  int32_t n_items;
+  int32_t total_waves;
+};
+
+template <typename T, int ORDER, int G, bool SKEW1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void pass2d_batch(
+    const BatchPassArgs<T> a) {
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wave >= a.total_waves) return;
+  int lo = 0, hi = a.n_items - 1;
+  while (lo < hi) {                                  // last item with wave_begin <= wave
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.items[mid].wave_begin <= wave) lo = mid; else hi = mid - 1;
+  }
+  const PassItem<T>* it = a.items + lo;
+  const int local = wave - it->wave_begin;
+  const int strips = it->strips;
+  PassWork<T> w;
+  w.cur = it->cur;
+  w.old = it->old;
+  w.out_a = it->out_a;
+  w.out_b = it->out_b;
+  w.ystar = it->ystar;
+  w.c2f = it->c2f;
+  w.src = nullptr;
+  w.field = it->field;
+  w.rhs = 0;
+  w.h = it->h;
+  w.c2c = it->c2c;
+  w.invx = it->invx;
+  w.invy = it->invy;
+  w.nx = it->nx;
+  w.ny = it->ny;
+  w.g = it->g;
+  w.flags = it->flags;
+  w.band = it->band;
+  w.nsrc = 0;
+#pragma unroll
+  for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = 0.0;
+  pass_body<T, ORDER, G, SKEW1>(w, local % strips, local / strips);
 }
 
 // y_out = sum_j c_j y*_j, j in ascending N, accumulated in FP64.
@@ -271,6 +377,36 @@ __global__ __launch_bounds__(256) void combine_kernel(const CombineArgs<T> a) {
   double v = a.c[0] * a.ystar[0][i];
   for (int j = 1; j < a.k; ++j) v = v + a.c[j] * a.ystar[j][i];
   a.yout[i] = (T)v;
+}
+
+// The same for a batch: block b belongs to the instance whose first block is
+// the largest block_begin <= b.
+template <typename T>
+struct CombineItem {
+  const double* ystar[GBS_MAX_SEQ];
+  double c[GBS_MAX_SEQ];
+  T* yout;
+  int64_t n;
+  int32_t k;
+  int32_t block_begin;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void combine_batch(const CombineItem<T>* items, int n_items,
+                                                     int total_blocks) {
+  const int b = blockIdx.x;
+  if (b >= total_blocks) return;
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  const CombineItem<T>* it = items + lo;
+  const int64_t i = (int64_t)(b - it->block_begin) * blockDim.x + threadIdx.x;
+  if (i >= it->n) return;
+  double v = it->c[0] * it->ystar[0][i];
+  for (int j = 1; j < it->k; ++j) v = v + it->c[j] * it->ystar[j][i];
+  it->yout[i] = (T)v;
 }
 
 }  // namespace gbs

@@ -127,3 +127,93 @@ class GBSPlan:
             except Exception:
                 pass
             self.handle = None
+
+
+class GBSBatch:
+    """Many independent 2-D acoustic instances (own grid, c^2 field or
+    constant, H) advanced together: one launch per pass round for the whole
+    batch, optionally replayed from a captured hipGraph.
+
+    instances: list of dicts with keys n = (nx, ny), H, and either c2 (float)
+    or c2_field (tensor [ny][nx]) with optional c_max."""
+
+    def __init__(self, instances, p, steps, w, fd_order=4, dtype=torch.float64, device="cuda",
+                 check_stability=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("GBSBatch needs a HIP device; there is no CPU path")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.dtype = dtype
+        flags = 0 if check_stability else B.FLAG_NO_STABILITY_CHECK
+        self.fields = []
+        probs = (B.Problem * len(instances))()
+        Hs = (ctypes.c_double * len(instances))()
+        self.shapes = []
+        for i, inst in enumerate(instances):
+            nx, ny = inst["n"]
+            ptr, c_max = None, 0.0
+            if inst.get("c2_field") is not None:
+                f = inst["c2_field"].to(device=self.device, dtype=dtype).contiguous()
+                self.fields.append(f)
+                ptr = f.data_ptr()
+                c_max = inst.get("c_max") or float(f.max().sqrt())
+            probs[i] = B.make_problem(B.ACOUSTIC2D, (nx, ny), fd_order, 1, _DT[dtype],
+                                      inst.get("c2", 1.0), ptr, c_max, flags)
+            Hs[i] = float(inst["H"])
+            self.shapes.append((1, 3, ny, nx))
+        self._probs, self._Hs = probs, Hs
+        self.scheme = B.make_scheme(p, steps, w)
+        nb = ctypes.c_size_t()
+        B.check(B.lib().gbs_batch_workspace_bytes(len(instances), probs, ctypes.byref(self.scheme),
+                                                  ctypes.byref(nb)))
+        self.workspace = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.handle = ctypes.c_void_p()
+        B.check(B.lib().gbs_batch_plan_create(ctypes.byref(self.handle), len(instances), probs,
+                                              ctypes.byref(self.scheme), Hs,
+                                              self.workspace.data_ptr(), self.workspace.numel(),
+                                              self.stream.cuda_stream))
+
+    def _ptrs(self, states):
+        if len(states) != len(self.shapes):
+            raise ValueError("need one state per instance")
+        for s, shp in zip(states, self.shapes):
+            if (s.device != self.device or s.dtype != self.dtype or not s.is_contiguous()
+                    or s.numel() != int(torch.Size(shp).numel())):
+                raise ValueError("state must be a contiguous %s tensor of %s elements on %s"
+                                 % (self.dtype, shp, self.device))
+        return (ctypes.c_void_p * len(states))(*[s.data_ptr() for s in states])
+
+    def step(self, states, n_macro=1):
+        """n_macro macro steps of every instance, in place."""
+        B.check(B.lib().gbs_batch_step(self.handle, int(n_macro), self._ptrs(states)))
+        return states
+
+    def set_variant(self, variant=0, band=0):
+        B.check(B.lib().gbs_batch_set_variant(self.handle, int(variant), int(band)))
+
+    def set_graph(self, on):
+        B.check(B.lib().gbs_batch_set_graph(self.handle, 1 if on else 0))
+
+    def autotune(self, states, macro_steps=2):
+        """Times the candidate kernels on ``states`` (which are advanced) and
+        keeps the fastest; returns (variant, band)."""
+        v, b = ctypes.c_int32(), ctypes.c_int32()
+        B.check(B.lib().gbs_batch_autotune(self.handle, self._ptrs(states), int(macro_steps),
+                                           ctypes.byref(v), ctypes.byref(b)))
+        return v.value, b.value
+
+    def updates_per_macro_step(self):
+        out = ctypes.c_double()
+        B.check(B.lib().gbs_batch_updates_per_macro_step(self.handle, ctypes.byref(out)))
+        return out.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                B.lib().gbs_batch_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None

@@ -30,3 +30,24 @@ CONFIG_ACOUSTIC2D = dict(name="acoustic2d_2048_fd4_order8_k6", n=2048, r=2, c2=1
                          scheme=schemes.ORDER8_K6,
                          H=stable_H(ISB_ORDER8_K6, 1.0, 1.0 / 2048, 2, SIGMA_FD4),
                          n_macro=500)
+
+
+# 64 independent 2-D acoustic instances, square sizes drawn from
+# {256, 512, 768, 1024}, log-normal c (sigma 0.2, correlation length 0.1,
+# seed 1000 + instance), order 8 over {2..12}, H at 0.8 of each instance's
+# limit, 100 macro steps.
+CONFIG_BATCH = dict(name="batch64_acoustic2d_lognormal_order8_k6", count=64,
+                    sizes=(256, 512, 768, 1024), size_seed=0, field_seed=1000, sigma=0.2,
+                    ell=0.1, r=2, scheme=schemes.ORDER8_K6, n_macro=100)
+
+
+def batch_instances(cfg=CONFIG_BATCH):
+    """[(n, c (speed field), H)] for the batch workload."""
+    from . import fields
+    out = []
+    for i, n in enumerate(fields.batch_sizes(cfg["count"], cfg["sizes"], cfg["size_seed"])):
+        c = fields.lognormal_speed((n, n), sigma=cfg["sigma"], ell=cfg["ell"],
+                                   seed=cfg["field_seed"] + i)
+        H = stable_H(ISB_ORDER8_K6, float(c.max()), 1.0 / n, 2, SIGMA_FD4)
+        out.append((n, c, H))
+    return out

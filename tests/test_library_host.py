@@ -84,7 +84,7 @@ def test_workspace_bytes_formula():
     steps, w = _cfg2()
     nb = _plan(B.ACOUSTIC2D, (64, 32), 8, steps, w, 1e-3)
     pts = 64 * 32 * 3
-    assert nb == pts * 8 + 4 * 6 * pts * 8      # acc + two pairs of levels per sequence
+    assert nb == 512 + pts * 8 + 4 * 6 * pts * 8      # sources + acc + two pairs per sequence
 
 
 def test_plan_stability_limit_is_sharp():
@@ -159,3 +159,32 @@ def test_algorithmic_bytes_of_both_schedules():
         assert out[2].value == pts * 7 * 24                     # first evaluation
     finally:
         B.plan_destroy(h)
+
+
+def test_batch_plan_validation_on_host():
+    steps, w = _cfg2()
+    sc = B.make_scheme(8, steps, w)
+    probs = (B.Problem * 3)()
+    for i, n in enumerate([(64, 64), (100, 72), (33, 40)]):
+        probs[i] = B.make_problem(B.ACOUSTIC2D, n)
+    Hs = (ctypes.c_double * 3)(1e-4, 1e-4, 1e-4)
+    nb = ctypes.c_size_t()
+    B.check(B.lib().gbs_batch_workspace_bytes(3, probs, ctypes.byref(sc), ctypes.byref(nb)))
+    h = ctypes.c_void_p()
+    B.check(B.lib().gbs_batch_plan_create(ctypes.byref(h), 3, probs, ctypes.byref(sc), Hs,
+                                          FAKE_WS, nb.value, None))
+    upd = ctypes.c_double()
+    B.check(B.lib().gbs_batch_updates_per_macro_step(h, ctypes.byref(upd)))
+    assert upd.value == (64 * 64 + 100 * 72 + 33 * 40) * 43
+    B.check(B.lib().gbs_batch_plan_destroy(h))
+    # one unstable instance rejects the batch
+    Hs[1] = 1.0
+    st = B.lib().gbs_batch_plan_create(ctypes.byref(h), 3, probs, ctypes.byref(sc), Hs,
+                                       FAKE_WS, nb.value, None)
+    assert st == B.GBS_EUNSTABLE
+    # 3-D instances are not batched
+    probs[2] = B.make_problem(B.ACOUSTIC3D, (16, 16, 16))
+    Hs[1] = 1e-4
+    st = B.lib().gbs_batch_plan_create(ctypes.byref(h), 3, probs, ctypes.byref(sc), Hs,
+                                       FAKE_WS, 1 << 40, None)
+    assert st == B.GBS_EUNSUPPORTED
