@@ -59,6 +59,82 @@ def cpu_baseline(cfg, y0):
                        "%.1f s, NumPy single thread" % dt)
 
 
+def bench_batch(args):
+    """64 uneven instances advanced in one batch (graph-replayed macro steps,
+    autotuned variant and band), against the plain FP64 form (one streaming
+    launch per sequence per leap-frog step, instance by instance)."""
+    import numpy as np
+    import torch
+    from paper_1907_11771_amd import binding as B
+    from paper_1907_11771_amd.plan import GBSBatch, GBSPlan, scheme_weights
+    from synth import workloads
+
+    cfg = workloads.CONFIG_BATCH
+    steps, w, _ = scheme_weights(cfg["scheme"])
+    dev = torch.device("cuda:0")
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    inst = workloads.batch_instances(cfg)
+    rng = np.random.default_rng(7)
+    y0 = [rng.standard_normal((1, 3, n, n)) for n, _, _ in inst]
+    spec = [dict(n=(n, n), H=H, c2_field=torch.from_numpy(c * c).to(dev), c_max=float(c.max()))
+            for n, c, H in inst]
+    batch = GBSBatch(spec, 8, steps, w, dtype=dtype, device=dev)
+    tune = [torch.from_numpy(a).to(dev, dtype) for a in y0]
+    variant, band = batch.autotune(tune, macro_steps=1)
+    del tune
+    batch.set_graph(True)
+    ys = [torch.from_numpy(a).to(dev, dtype) for a in y0]
+    batch.step(ys, n_macro=max(args.warmup, 1))
+    ys = [torch.from_numpy(a).to(dev, dtype) for a in y0]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    batch.step(ys, n_macro=args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    upd = batch.updates_per_macro_step() * args.steps
+
+    # accuracy of this run against the FP64 batch after the same steps
+    err = None
+    if dtype == torch.float32:
+        ref = GBSBatch(spec, 8, steps, w, dtype=torch.float64, device=dev)
+        ref.set_variant(variant, band)
+        yr = [torch.from_numpy(a).to(dev) for a in y0]
+        ref.step(yr, n_macro=args.steps)
+        err = max(float((a.double() - b).abs().max() / b.abs().max()) for a, b in zip(ys, yr))
+        del ref, yr
+
+    # the plain FP64 form on the same instances (a few macro steps, per macro step)
+    plain_steps = 3
+    plain_s = 0.0
+    for (n, c, H), a in zip(inst, y0):
+        pl = GBSPlan(B.ACOUSTIC2D, (n, n), 8, steps, w, H, dtype=torch.float64,
+                     c2_field=torch.from_numpy(c * c).to(dev), c_max=float(c.max()), device=dev)
+        pl.set_variant(B.VARIANT_PLAIN)
+        y = torch.from_numpy(a).to(dev)
+        pl.step(y, y, n_macro=1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pl.step(y, y, n_macro=plain_steps)
+        torch.cuda.synchronize()
+        plain_s += time.perf_counter() - t
+        del pl, y
+    plain_ms = plain_s * 1e3 / plain_steps
+    rec = dict(
+        metric="grid-pt RHS updates/s", value=upd / dt, unit="grid-pt RHS updates/s",
+        n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=dt * 1e3 / args.steps,
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype=args.dtype,
+        data="synthetic",
+        config=dict(workload=cfg["name"], instances=len(inst),
+                    sizes=sorted(set(n for n, _, _ in inst)), points=sum(n * n for n, _, _ in inst),
+                    evals_per_macro_step=1 + sum(steps), graph=True,
+                    autotuned=dict(variant=variant, band=band)),
+        plain_fp64_ms_per_step=plain_ms,
+        speedup_vs_plain_fp64=plain_ms / (dt * 1e3 / args.steps),
+        max_rel_err_vs_fp64=err,
+    )
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +145,12 @@ def main():
                     help="stepping-kernel variant (0 = the library's choice)")
     ap.add_argument("--band", type=int, default=0,
                     help="rows per band of the temporally blocked passes (0 = default)")
+    ap.add_argument("--workload", default="acoustic2d",
+                    choices=["acoustic2d", "batch64"],
+                    help="acoustic2d: the 2048^2 FP64 workload (default); batch64: 64 "
+                         "uneven instances in one batch")
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"],
+                    help="stepping precision of the batch workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -92,6 +174,9 @@ def main():
     from paper_1907_11771_amd import binding as B
     from paper_1907_11771_amd.plan import GBSPlan, scheme_weights
     from synth import fields, workloads
+
+    if args.workload == "batch64":
+        return bench_batch(args)
 
     cfg = workloads.CONFIG_ACOUSTIC2D
     n = cfg["n"]

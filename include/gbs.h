@@ -184,6 +184,8 @@ int gbs_step(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void*
  *   GBS_VARIANT_TEMPORAL_S5/S6  at most 5 / 6 evaluations per pass, the
  *                           levels of one row step evaluated independently
  *                           (one more row of time skew between levels)
+ *   GBS_VARIANT_PLAIN       the unfused reference form: one streaming launch
+ *                           per sequence per leap-frog step (every operator)
  * The temporally blocked variants agree with the streaming ones to
  * rounding (the combination is summed in the same order, the products may
  * be contracted differently).
@@ -201,7 +203,8 @@ enum {
   GBS_VARIANT_TEMPORAL = 6,
   GBS_VARIANT_TEMPORAL4 = 7,
   GBS_VARIANT_TEMPORAL_S5 = 8,
-  GBS_VARIANT_TEMPORAL_S6 = 9
+  GBS_VARIANT_TEMPORAL_S6 = 9,
+  GBS_VARIANT_PLAIN = 10
 };
 int gbs_plan_set_variant(gbs_plan* plan, int32_t variant);
 int gbs_plan_set_band(gbs_plan* plan, int32_t rows);

@@ -19,6 +19,7 @@ FLAG_NO_STABILITY_CHECK = 1
 VARIANT_AUTO, VARIANT_FLAT, VARIANT_MARCH8, VARIANT_MARCH16 = 0, 1, 2, 3
 VARIANT_MARCH8_NT, VARIANT_MARCH16_NT = 4, 5
 VARIANT_TEMPORAL, VARIANT_TEMPORAL4, VARIANT_TEMPORAL_S5, VARIANT_TEMPORAL_S6 = 6, 7, 8, 9
+VARIANT_PLAIN = 10
 MAX_SEQ = 16
 MAX_SRC = 16
 

@@ -318,6 +318,15 @@ void launch_lf(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gx, unsigned 
       default: break;
     }
   }
+  if (resolve_variant(P) == GBS_VARIANT_PLAIN) {
+    // one launch per sequence: the unfused reference form
+    StepArgs<T> one = sa;
+    for (int i = 0; i < n; ++i) {
+      one.seq[0] = sa.seq[i];
+      hipLaunchKernelGGL((lf_kernel<T, ORDER, OP>), dim3(gx, 1, gz), dim3(256), 0, P->stream, one);
+    }
+    return;
+  }
   hipLaunchKernelGGL((lf_kernel<T, ORDER, OP>), dim3(gx, n, gz), dim3(256), 0, P->stream, sa);
 }
 
@@ -527,9 +536,9 @@ extern "C" int gbs_step(gbs_plan* P, double t0, int32_t n_macro, const void* y_i
 
 extern "C" int gbs_plan_set_variant(gbs_plan* P, int32_t variant) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
-  if (variant < GBS_VARIANT_AUTO || variant > GBS_VARIANT_TEMPORAL_S6)
+  if (variant < GBS_VARIANT_AUTO || variant > GBS_VARIANT_PLAIN)
     return fail(GBS_EINVAL, "unknown variant %d", variant);
-  if (variant >= GBS_VARIANT_MARCH8 && P->prob.op != GBS_ACOUSTIC2D)
+  if (variant >= GBS_VARIANT_MARCH8 && variant != GBS_VARIANT_PLAIN && P->prob.op != GBS_ACOUSTIC2D)
     return fail(GBS_EUNSUPPORTED, "this variant is built for the 2-D acoustic operator only");
   P->variant = variant;
   return GBS_OK;

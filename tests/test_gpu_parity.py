@@ -126,7 +126,7 @@ def test_kernel_variants_agree_bitwise(dtype):
     y0 = to_dev(np.random.default_rng(3).standard_normal((2, 3, ny, nx)), dtype)
     outs = []
     for v in (B.VARIANT_FLAT, B.VARIANT_MARCH8, B.VARIANT_MARCH16, B.VARIANT_MARCH8_NT,
-              B.VARIANT_MARCH16_NT):
+              B.VARIANT_MARCH16_NT, B.VARIANT_PLAIN):
         plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, n_rhs=2, dtype=dtype,
                         c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
         plan.set_variant(v)
