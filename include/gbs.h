@@ -88,6 +88,7 @@ typedef struct gbs_scheme {
 
 #define GBS_MAX_SEQ 16
 #define GBS_MAX_SRC 16
+#define GBS_MAX_REC 1024
 
 typedef struct gbs_plan gbs_plan;
 
@@ -123,7 +124,8 @@ int gbs_isb(int32_t k, const int32_t* steps, const double* weights, double* isb_
 
 /*
  * gbs_plan_workspace_bytes — device workspace needed by a plan: a 512-byte
- * source table, one FP64 accumulator state plus, per sequence, two levels
+ * source table, a 16 KiB receiver table, one FP64 accumulator state plus,
+ * per sequence, two levels
  * in the plan's dtype
  * (four for GBS_ACOUSTIC2D, whose temporally blocked passes read one pair
  * and write the other), each 256-byte aligned.
@@ -239,6 +241,41 @@ int gbs_plan_algorithmic_bytes(const gbs_plan* plan, double* step_bytes, int64_t
 int gbs_plan_updates_per_macro_step(const gbs_plan* plan, double* updates);
 
 int gbs_plan_destroy(gbs_plan* plan);
+
+/*
+ * Receivers and the adjoint (acoustic plans).  The paper defines only the
+ * forward step (Sect. 2.1, eq. GBS; Sect. 3.2); the adjoint below is the
+ * exact transpose of that discrete step for f(t, y) = A y + s(t):
+ * each sequence's recurrence run backwards (leap-frog, averaging, forward
+ * Euler, the shared first evaluation), plus the gradient with respect to
+ * the coefficient field c^2.
+ *
+ * gbs_plan_set_receivers — n_rec <= GBS_MAX_REC receivers of the pressure:
+ *   rhs[r], flat_index[r] (within one field) host arrays, copied into the
+ *   workspace (synchronises the plan's stream).
+ * gbs_step_record — as gbs_step, and after every macro step m writes
+ *   traces[m][r] = p[rhs_r][flat_index_r] of the new state (device array
+ *   [n_macro][n_rec] in the plan's dtype).
+ * gbs_plan_adjoint_workspace_bytes — scratch for gbs_adjoint_step: the
+ *   forward levels of one sequence (N_max of them), two adjoint levels and
+ *   two FP64 accumulator states.
+ * gbs_adjoint_step — one macro step backwards.  y_in: forward state at t0
+ *   (start of the macro step); ybar (device, in/out): on entry the adjoint
+ *   of the state at t0 + H, on return the adjoint of the state at t0;
+ *   trace_bar (device [n_rec], nullable): adjoint of the traces recorded at
+ *   t0 + H, added to ybar's pressure at the receivers first; grad_c2
+ *   (device FP64 [Z][Y][X], nullable, needs a c^2 field): dL/dc^2 of this
+ *   macro step is added to it.  The forward levels are recomputed from y_in
+ *   (with the plan's sources) in the adjoint workspace.
+ */
+int gbs_plan_set_receivers(gbs_plan* plan, int32_t n_rec, const int32_t* rhs,
+                           const int64_t* flat_index);
+int gbs_step_record(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void* y_out,
+                    void* traces);
+int gbs_plan_adjoint_workspace_bytes(const gbs_plan* plan, size_t* bytes);
+int gbs_adjoint_step(gbs_plan* plan, double t0, const void* y_in, void* ybar,
+                     const void* trace_bar, double* grad_c2, void* adj_workspace,
+                     size_t adj_workspace_bytes);
 
 /*
  * Batches of independent 2-D acoustic instances (GBS_ACOUSTIC2D, n_rhs = 1,

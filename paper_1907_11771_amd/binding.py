@@ -22,6 +22,7 @@ VARIANT_TEMPORAL, VARIANT_TEMPORAL4, VARIANT_TEMPORAL_S5, VARIANT_TEMPORAL_S6 = 
 VARIANT_PLAIN = 10
 MAX_SEQ = 16
 MAX_SRC = 16
+MAX_REC = 1024
 
 _NAMES = {GBS_EINVAL: "EINVAL", GBS_ESTEPS: "ESTEPS", GBS_EORDER: "EORDER",
           GBS_ESINGULAR: "ESINGULAR", GBS_EUNSTABLE: "EUNSTABLE", GBS_EDEVICE: "EDEVICE",
@@ -80,6 +81,10 @@ def lib():
             "gbs_plan_updates_per_macro_step": [vp, P(dbl)],
             "gbs_plan_algorithmic_bytes": [vp, P(dbl), P(i64), P(dbl), P(i64)],
             "gbs_plan_destroy": [vp],
+"gbs_plan_set_receivers": [vp, i32, P(i32), P(i64)],
+            "gbs_step_record": [vp, dbl, i32, vp, vp, vp],
+            "gbs_plan_adjoint_workspace_bytes": [vp, P(sz)],
+            "gbs_adjoint_step": [vp, dbl, vp, vp, vp, vp, vp, sz],
             "gbs_batch_workspace_bytes": [i32, P(Problem), P(Scheme), P(sz)],
             "gbs_batch_plan_create": [P(vp), i32, P(Problem), P(Scheme), P(dbl), vp, sz, vp],
             "gbs_batch_set_variant": [vp, i32, i32],

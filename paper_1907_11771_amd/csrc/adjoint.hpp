@@ -1,0 +1,270 @@
+// Discrete adjoint of one extrapolated GBS macro step for the acoustic
+// operators (2-D and 3-D), and the receiver gather / injection kernels.
+//
+// The paper defines the forward step only (Sect. 2.1, eq. GBS; Sect. 3.2).
+// For f(t, y) = A y + s(t) (A linear in y and, through C = diag(c^2), in the
+// coefficient field) the transpose of one sequence is its recurrence run
+// backwards.  With lambda_n the adjoint of level y_n and w = c_j ybar_out:
+//   lambda_{N+1} = w/4, lambda_N = w/2, lambda_{N-1} = w/4 (averaging),
+//   for n = N..1:  lambda_n += 2h A^T lambda_{n+1};  lambda_{n-1} += lambda_{n+1},
+//   ybar_0 += lambda_0 + lambda_1,  Fbar_0 += h lambda_1   (forward Euler),
+// and once for all sequences ybar_0 += A^T Fbar_0 (shared first evaluation).
+// Two buffers carry (lambda_{n+1} final, lambda_n partial): one step reads
+// the first at the stencil's neighbours and updates the second in place,
+// then the roles swap, as in the forward leap-frog.  The gradient with
+// respect to c^2 collects a * lambda_p * (-div v_n) for every application of
+// A with factor a (2h, or h_j for the shared first evaluation), in FP64.
+//
+// Periodic centred differences are antisymmetric (D^T = -D), so
+//   (A^T w)_p = sum_k D_k w_{v_k},   (A^T w)_{v_k} = D_k (c^2 w_p).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace gbs {
+
+// sum_m W_m (c2[i+m] u[i+m] - c2[i-m] u[i-m]) along one axis (product
+// formed at each neighbour).
+template <typename T, int ORDER>
+__device__ __forceinline__ T dsum_c2(const T* __restrict__ u, const T* __restrict__ c2f, T c2c,
+                                     int i, int n, int64_t stride) {
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < Fd<ORDER>::R; ++k) {
+    const int64_t iu = (int64_t)wrap(i + k + 1, n) * stride;
+    const int64_t id = (int64_t)wrap(i - k - 1, n) * stride;
+    const T up = (c2f ? c2f[iu] : c2c) * u[iu];
+    const T dn = (c2f ? c2f[id] : c2c) * u[id];
+    s += Fd<ORDER>::template w<T>(k) * (up - dn);
+  }
+  return s;
+}
+
+// A^T w at (x, y, z) of one right-hand side w (fields p, v...), and -div v
+// of a state s at the same point.
+template <typename T, int ORDER, int OP>
+__device__ __forceinline__ void eval_AT(const T* __restrict__ w, const T* __restrict__ c2f, T c2c,
+                                        int x, int y, int z, const Geometry& g, T invx, T invy,
+                                        T invz, T* out) {
+  constexpr int D = OP == OP_AC2D ? 2 : 3;
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  const int64_t xline = (int64_t)z * plane + (int64_t)y * g.nx;
+  const int64_t yline = (int64_t)z * plane + x;
+  const int64_t zline = (int64_t)y * g.nx + x;
+  const T* p = w;
+  const T* c2x = c2f ? c2f + xline : nullptr;
+  const T* c2y = c2f ? c2f + yline : nullptr;
+  out[0] = invx * dsum<T, ORDER>(w + g.field + xline, x, g.nx, 1) +
+           invy * dsum<T, ORDER>(w + 2 * g.field + yline, y, g.ny, g.nx);
+  out[1] = invx * dsum_c2<T, ORDER>(p + xline, c2x, c2c, x, g.nx, 1);
+  out[2] = invy * dsum_c2<T, ORDER>(p + yline, c2y, c2c, y, g.ny, g.nx);
+  if constexpr (D == 3) {
+    const T* c2z = c2f ? c2f + zline : nullptr;
+    out[0] += invz * dsum<T, ORDER>(w + 3 * g.field + zline, z, g.nz, plane);
+    out[3] = invz * dsum_c2<T, ORDER>(p + zline, c2z, c2c, z, g.nz, plane);
+  }
+}
+
+template <typename T, int ORDER, int OP>
+__device__ __forceinline__ T neg_div(const T* __restrict__ s, int x, int y, int z,
+                                     const Geometry& g, T invx, T invy, T invz) {
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  const int64_t xline = (int64_t)z * plane + (int64_t)y * g.nx;
+  const int64_t yline = (int64_t)z * plane + x;
+  T d = invx * dsum<T, ORDER>(s + g.field + xline, x, g.nx, 1) +
+        invy * dsum<T, ORDER>(s + 2 * g.field + yline, y, g.ny, g.nx);
+  if constexpr (OP == OP_AC3D) {
+    const int64_t zline = (int64_t)y * g.nx + x;
+    d += invz * dsum<T, ORDER>(s + 3 * g.field + zline, z, g.nz, plane);
+  }
+  return -d;
+}
+
+template <typename T>
+struct AdjArgs {
+  Geometry g;
+  const T* c2f;
+  T c2c, invx, invy, invz;
+  const T* ybar;        // adjoint at the macro step's end (first kernel)
+  const T* level;       // forward level y_n (for -div v_n)
+  T* P;                 // lambda_{n+1} (final), read at the neighbours
+  T* Q;                 // lambda_n (partial), updated in place
+  double* yacc;         // sum_j (lambda_0 + lambda_1)
+  double* facc;         // sum_j h_j lambda_1
+  double* grad;         // dL/dc^2, FP64, [Z][Y][X], or null
+  double cw;            // c_j
+  double h;             // h_j
+  int32_t last;         // this step is n = 1: fold into yacc / facc
+  int32_t first_seq;    // the first sequence writes yacc / facc instead of adding
+  int32_t nrhs;         // right-hand sides (looped over by each thread)
+};
+
+// Step n = N of sequence j: reads w = c_j ybar at the neighbours, writes
+// P = lambda_N (final) and Q = lambda_{N-1} (partial, = w/2).
+template <typename T, int ORDER, int OP>
+__global__ __launch_bounds__(256) void adj_first_kernel(const AdjArgs<T> a) {
+  constexpr int F = NFields<OP>::F;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.g.field) return;
+  int x, y, z;
+  decompose(idx, a.g, x, y, z);
+  double gsum = 0.0;
+  for (int r = 0; r < a.nrhs; ++r) {
+    const int64_t base = (int64_t)r * a.g.state;
+    T at[F];
+    eval_AT<T, ORDER, OP>(a.ybar + base, a.c2f, a.c2c, x, y, z, a.g, a.invx, a.invy, a.invz, at);
+    const T cq = (T)(0.25 * a.cw), ch = (T)(0.5 * a.cw);
+    const T h2 = (T)(2.0 * a.h);
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+      const int64_t e = base + q * a.g.field + idx;
+      const T yb = a.ybar[e];
+      a.P[e] = ch * yb + h2 * (cq * at[q]);           // lambda_N
+      a.Q[e] = ch * yb;                               // lambda_{N-1} so far
+    }
+    if (a.grad) {
+      const T dv = neg_div<T, ORDER, OP>(a.level + base, x, y, z, a.g, a.invx, a.invy, a.invz);
+      gsum += 2.0 * a.h * ((double)cq * (double)a.ybar[base + idx]) * (double)dv;
+    }
+  }
+  if (a.grad) a.grad[idx] += gsum;
+}
+
+// Step n < N: Q += 2h A^T P; gradient from P and y_n; at n = 1 the forward
+// Euler transpose is folded in.
+template <typename T, int ORDER, int OP>
+__global__ __launch_bounds__(256) void adj_lf_kernel(const AdjArgs<T> a) {
+  constexpr int F = NFields<OP>::F;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.g.field) return;
+  int x, y, z;
+  decompose(idx, a.g, x, y, z);
+  const T h2 = (T)(2.0 * a.h);
+  double gsum = 0.0;
+  for (int r = 0; r < a.nrhs; ++r) {
+    const int64_t base = (int64_t)r * a.g.state;
+    T at[F];
+    eval_AT<T, ORDER, OP>(a.P + base, a.c2f, a.c2c, x, y, z, a.g, a.invx, a.invy, a.invz, at);
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+      const int64_t e = base + q * a.g.field + idx;
+      const T qn = a.Q[e] + h2 * at[q];
+      if (!a.last) {
+        a.Q[e] = qn;
+      } else {
+        // here qn = lambda_1 (final) and P = lambda_2 = lambda_0 (its only term)
+        const double l1 = (double)qn;
+        const double v0 = l1 + (double)a.P[e];       // lambda_0 + lambda_1
+        const double f0 = a.h * l1;                  // h_j lambda_1
+        if (a.first_seq) {
+          a.yacc[e] = v0;
+          a.facc[e] = f0;
+        } else {
+          a.yacc[e] += v0;
+          a.facc[e] += f0;
+        }
+      }
+    }
+    if (a.grad) {
+      const T dv = neg_div<T, ORDER, OP>(a.level + base, x, y, z, a.g, a.invx, a.invy, a.invz);
+      gsum += 2.0 * a.h * (double)a.P[base + idx] * (double)dv;
+    }
+  }
+  if (a.grad) a.grad[idx] += gsum;
+}
+
+template <typename T>
+struct AdjFinalArgs {
+  Geometry g;
+  const T* c2f;
+  T c2c;
+  double invx, invy, invz;
+  const double* yacc;
+  const double* facc;
+  const T* y0;          // forward state at the macro step's start
+  T* ybar;              // out: adjoint at the macro step's start
+  double* grad;
+  int32_t nrhs;
+};
+
+// ybar_0 = yacc + A^T facc (FP64), gradient of the shared first evaluation.
+template <typename T, int ORDER, int OP>
+__global__ __launch_bounds__(256) void adj_final_kernel(const AdjFinalArgs<T> a) {
+  constexpr int F = NFields<OP>::F;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.g.field) return;
+  int x, y, z;
+  decompose(idx, a.g, x, y, z);
+  const int64_t plane = (int64_t)a.g.nx * a.g.ny;
+  const int64_t xline = (int64_t)z * plane + (int64_t)y * a.g.nx;
+  const int64_t yline = (int64_t)z * plane + x;
+  const int64_t zline = (int64_t)y * a.g.nx + x;
+  auto c2at = [&](int64_t i) { return a.c2f ? (double)a.c2f[i] : (double)a.c2c; };
+  double gsum = 0.0;
+  for (int r = 0; r < a.nrhs; ++r) {
+    const int64_t base = (int64_t)r * a.g.state;
+    const double* fp = a.facc + base;
+    double at[F];
+    at[0] = a.invx * dsum<double, ORDER>(fp + a.g.field + xline, x, a.g.nx, 1) +
+            a.invy * dsum<double, ORDER>(fp + 2 * a.g.field + yline, y, a.g.ny, a.g.nx);
+    double sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int k = 0; k < Fd<ORDER>::R; ++k) {
+      const int64_t xu = xline + wrap(x + k + 1, a.g.nx), xd = xline + wrap(x - k - 1, a.g.nx);
+      const int64_t yu = yline + (int64_t)wrap(y + k + 1, a.g.ny) * a.g.nx;
+      const int64_t yd = yline + (int64_t)wrap(y - k - 1, a.g.ny) * a.g.nx;
+      const double wk = Fd<ORDER>::template w<double>(k);
+      sx += wk * (c2at(xu) * fp[xu] - c2at(xd) * fp[xd]);
+      sy += wk * (c2at(yu) * fp[yu] - c2at(yd) * fp[yd]);
+      if constexpr (OP == OP_AC3D) {
+        const int64_t zu = zline + (int64_t)wrap(z + k + 1, a.g.nz) * plane;
+        const int64_t zd = zline + (int64_t)wrap(z - k - 1, a.g.nz) * plane;
+        sz += wk * (c2at(zu) * fp[zu] - c2at(zd) * fp[zd]);
+      }
+    }
+    at[1] = a.invx * sx;
+    at[2] = a.invy * sy;
+    if constexpr (OP == OP_AC3D) {
+      at[0] += a.invz * dsum<double, ORDER>(fp + 3 * a.g.field + zline, z, a.g.nz, plane);
+      at[3] = a.invz * sz;
+    }
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+      const int64_t e = base + q * a.g.field + idx;
+      a.ybar[e] = (T)(a.yacc[e] + at[q]);
+    }
+    if (a.grad) {
+      const T dv = neg_div<T, ORDER, OP>(a.y0 + base, x, y, z, a.g, (T)a.invx, (T)a.invy,
+                                         (T)a.invz);
+      gsum += fp[idx] * (double)dv;
+    }
+  }
+  if (a.grad) a.grad[idx] += gsum;
+}
+
+// Receivers: traces[r] = p[rhs_r][idx_r] of a state; injection adds
+// tbar[r] to the pressure of an adjoint state.
+struct RecDesc {
+  int64_t idx;
+  int32_t rhs;
+  int32_t pad;
+};
+
+template <typename T>
+__global__ void gather_kernel(const T* __restrict__ y, int64_t state, const RecDesc* rec, int n,
+                              T* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  out[r] = y[(int64_t)rec[r].rhs * state + rec[r].idx];
+}
+
+// One thread per receiver, in receiver order, so that receivers sharing a
+// grid point add up deterministically.
+template <typename T>
+__global__ void inject_kernel(T* __restrict__ ybar, int64_t state, const RecDesc* rec, int n,
+                              const T* __restrict__ tbar) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int r = 0; r < n; ++r) ybar[(int64_t)rec[r].rhs * state + rec[r].idx] += tbar[r];
+}
+
+}  // namespace gbs

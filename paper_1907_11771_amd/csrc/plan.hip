@@ -26,6 +26,7 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "temporal.hpp"
+#include "adjoint.hpp"
 
 namespace gbs {
 
@@ -66,6 +67,9 @@ struct gbs_plan {
   int nsrc = 0;
   SrcDesc src[GBS_MAX_SRC];
   SrcDesc* src_dev = nullptr;
+  // receivers (device table in the workspace)
+  int nrec = 0;
+  RecDesc* rec_dev = nullptr;
   double f0 = 0, delay = 0;
   // leap-frog kernel variant (GBS_VARIANT_*) and rows per band of the
   // temporally blocked passes
@@ -149,11 +153,12 @@ int validate_scheme(const gbs_scheme* s) {
 int levels_per_seq(const gbs_problem* p) { return p->op == GBS_ACOUSTIC2D ? 4 : 2; }
 
 constexpr size_t kSrcBytes = (GBS_MAX_SRC * sizeof(SrcDesc) + kAlign - 1) / kAlign * kAlign;
+constexpr size_t kRecBytes = (GBS_MAX_REC * sizeof(RecDesc) + kAlign - 1) / kAlign * kAlign;
 
 size_t workspace_bytes(const gbs_problem* p, int k) {
   const int64_t pts = p->n[0] * p->n[1] * p->n[2];
   const size_t elems = (size_t)p->n_rhs * fields_of(p->op) * pts;
-  return kSrcBytes + align_up(elems * 8) +
+  return kSrcBytes + kRecBytes + align_up(elems * 8) +
          levels_per_seq(p) * (size_t)k * align_up(elems * dsize(p->dtype));
 }
 
@@ -470,6 +475,8 @@ extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gb
     char* base = (char*)workspace;
     P->src_dev = (SrcDesc*)base;
     base += kSrcBytes;
+    P->rec_dev = (RecDesc*)base;
+    base += kRecBytes;
     P->acc = (double*)base;
     base += align_up(elems * 8);
     const size_t lb = align_up(elems * dsize(prob->dtype));
@@ -1068,4 +1075,201 @@ extern "C" int gbs_batch_plan_destroy(gbs_batch_plan* B) {
   if (B->ev_out) hipEventDestroy(B->ev_out);
   delete B;
   return GBS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Receivers, recorded forward runs and the adjoint macro step.
+// ---------------------------------------------------------------------------
+
+extern "C" int gbs_plan_set_receivers(gbs_plan* P, int32_t n_rec, const int32_t* rhs,
+                                      const int64_t* flat_index) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  if (n_rec < 0 || n_rec > GBS_MAX_REC) return fail(GBS_EINVAL, "n_rec out of range");
+  if (P->prob.op == GBS_ADVECT1D && n_rec) return fail(GBS_EINVAL, "receivers need an acoustic plan");
+  if (n_rec && (!rhs || !flat_index)) return fail(GBS_EINVAL, "receiver arrays are null");
+  std::vector<RecDesc> r(std::max(n_rec, 1));
+  for (int i = 0; i < n_rec; ++i) {
+    if (rhs[i] < 0 || rhs[i] >= P->prob.n_rhs || flat_index[i] < 0 || flat_index[i] >= P->field)
+      return fail(GBS_EINVAL, "receiver %d out of range", i);
+    r[i].idx = flat_index[i];
+    r[i].rhs = rhs[i];
+    r[i].pad = 0;
+  }
+  if (n_rec && (hipMemcpyAsync(P->rec_dev, r.data(), n_rec * sizeof(RecDesc),
+                               hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+                hipStreamSynchronize(P->stream) != hipSuccess))
+    return fail(GBS_EDEVICE, "copying the receivers to the workspace failed");
+  P->nrec = n_rec;
+  return GBS_OK;
+}
+
+extern "C" int gbs_step_record(gbs_plan* P, double t0, int32_t n_macro, const void* y_in,
+                               void* y_out, void* traces) {
+  if (!P || !y_in || !y_out || (!traces && P->nrec)) return fail(GBS_EINVAL, "null argument");
+  if (n_macro < 0) return fail(GBS_EINVAL, "n_macro must be >= 0");
+  const size_t b = dsize(P->prob.dtype);
+  for (int m = 0; m < n_macro; ++m) {
+    int st = gbs_step(P, t0 + m * P->H, 1, m == 0 ? y_in : y_out, y_out);
+    if (st) return st;
+    if (P->nrec) {
+      const unsigned blocks = (unsigned)((P->nrec + 255) / 256);
+      char* out = (char*)traces + (size_t)m * P->nrec * b;
+      if (P->prob.dtype == GBS_F64)
+        hipLaunchKernelGGL(gather_kernel<double>, dim3(blocks), dim3(256), 0, P->stream,
+                           (const double*)y_out, P->state, P->rec_dev, P->nrec, (double*)out);
+      else
+        hipLaunchKernelGGL(gather_kernel<float>, dim3(blocks), dim3(256), 0, P->stream,
+                           (const float*)y_out, P->state, P->rec_dev, P->nrec, (float*)out);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GBS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return GBS_OK;
+}
+
+namespace {
+
+size_t adjoint_bytes(const gbs_plan* P) {
+  const size_t elems = (size_t)P->prob.n_rhs * P->state;
+  const size_t lb = align_up(elems * dsize(P->prob.dtype));
+  return (size_t)(P->nmax + 2) * lb + 2 * align_up(elems * 8);
+}
+
+template <typename T, int ORDER, int OP>
+int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, double* grad,
+                char* ws) {
+  const size_t elems = (size_t)P->prob.n_rhs * P->state;
+  const size_t lb = align_up(elems * sizeof(T));
+  std::vector<T*> L(P->nmax + 1, nullptr);   // L[1..nmax]: forward levels of one sequence
+  for (int s = 1; s <= P->nmax; ++s) L[s] = (T*)(ws + (size_t)(s - 1) * lb);
+  T* bufA = (T*)(ws + (size_t)P->nmax * lb);
+  T* bufB = (T*)(ws + (size_t)(P->nmax + 1) * lb);
+  double* yacc = (double*)(ws + (size_t)(P->nmax + 2) * lb);
+  double* facc = (double*)((char*)yacc + align_up(elems * 8));
+  const unsigned gx = (unsigned)((P->field + 255) / 256);
+  const unsigned gz = (unsigned)P->prob.n_rhs;
+  hipStream_t s = P->stream;
+
+  if (tbar && P->nrec)
+    hipLaunchKernelGGL(inject_kernel<T>, dim3(1), dim3(64), 0, s, ybar, P->state, P->rec_dev,
+                       P->nrec, tbar);
+
+  FirstArgs<T> fa;
+  StepArgs<T> sa;
+  std::memset(&fa, 0, sizeof(fa));
+  std::memset(&sa, 0, sizeof(sa));
+  fill_geometry<T>(P, fa.g, fa.c2c, fa.c2f, fa.invx, fa.invy, fa.invz);
+  fill_geometry<T>(P, sa.g, sa.c2c, sa.c2f, sa.invx, sa.invy, sa.invz);
+  std::memcpy(fa.src, P->src, sizeof(P->src));
+  std::memcpy(sa.src, P->src, sizeof(P->src));
+  AdjArgs<T> aa;
+  std::memset(&aa, 0, sizeof(aa));
+  T c2c_dummy;
+  const T* c2f_dummy;
+  fill_geometry<T>(P, aa.g, c2c_dummy, c2f_dummy, aa.invx, aa.invy, aa.invz);
+  aa.c2f = c2f_dummy;
+  aa.c2c = c2c_dummy;
+  aa.ybar = ybar;
+  aa.yacc = yacc;
+  aa.facc = facc;
+  aa.grad = grad;
+  aa.nrhs = P->prob.n_rhs;
+
+  for (int r = 0; r < P->k; ++r) {
+    const int j = P->order[r];
+    const int N = P->steps[j];
+    const double h = P->H / N;
+    // forward levels y_1..y_N of sequence j (y_0 is the input state)
+    fa.y0 = y0;
+    fa.nseq = 1;
+    fa.out[0] = L[1];
+    fa.h[0] = (T)h;
+    fa.amp = P->nsrc ? ricker(t0, P->f0, P->delay) : 0.0;
+    hipLaunchKernelGGL((first_kernel<T, ORDER, OP>), dim3(gx, 1, gz), dim3(256), 0, s, fa);
+    for (int st = 1; st <= N - 1; ++st) {
+      SeqDesc<T>& d = sa.seq[0];
+      d.cur = L[st];
+      d.old = st == 1 ? y0 : L[st - 1];
+      d.out = L[st + 1];
+      d.h2 = (T)(2.0 * h);
+      d.cw = 0.0;
+      d.amp = P->nsrc ? ricker(t0 + st * h, P->f0, P->delay) : 0.0;
+      d.mode = 0;
+      hipLaunchKernelGGL((lf_kernel<T, ORDER, OP>), dim3(gx, 1, gz), dim3(256), 0, s, sa);
+    }
+    // transposed sequence
+    aa.cw = P->w[j];
+    aa.h = h;
+    aa.first_seq = r == 0;
+    aa.level = L[N];
+    aa.P = bufA;
+    aa.Q = bufB;
+    aa.last = 0;
+    hipLaunchKernelGGL((adj_first_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
+    for (int n = N - 1; n >= 1; --n) {
+      const bool a_is_p = ((N - 1 - n) % 2) == 0;
+      aa.P = a_is_p ? bufA : bufB;
+      aa.Q = a_is_p ? bufB : bufA;
+      aa.level = n == 0 ? y0 : L[n];
+      aa.last = n == 1;
+      hipLaunchKernelGGL((adj_lf_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
+    }
+  }
+  AdjFinalArgs<T> fz;
+  std::memset(&fz, 0, sizeof(fz));
+  T ix, iy, iz;
+  fill_geometry<T>(P, fz.g, fz.c2c, fz.c2f, ix, iy, iz);
+  const double den = P->prob.fd_order == 8 ? 840.0 : 12.0;
+  fz.invx = (double)P->prob.n[0] / den;
+  fz.invy = (double)P->prob.n[1] / den;
+  fz.invz = (double)P->prob.n[2] / den;
+  fz.yacc = yacc;
+  fz.facc = facc;
+  fz.y0 = y0;
+  fz.ybar = ybar;
+  fz.grad = grad;
+  fz.nrhs = P->prob.n_rhs;
+  hipLaunchKernelGGL((adj_final_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, fz);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GBS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return GBS_OK;
+}
+
+template <typename T>
+int adjoint_dispatch(gbs_plan* P, double t0, const void* y0, void* ybar, const void* tbar,
+                     double* grad, char* ws) {
+  const T* a = (const T*)y0;
+  T* b = (T*)ybar;
+  const T* c = (const T*)tbar;
+  if (P->prob.fd_order == 4) {
+    if (P->prob.op == GBS_ACOUSTIC2D) return adjoint_run<T, 4, OP_AC2D>(P, t0, a, b, c, grad, ws);
+    return adjoint_run<T, 4, OP_AC3D>(P, t0, a, b, c, grad, ws);
+  }
+  if (P->prob.op == GBS_ACOUSTIC2D) return adjoint_run<T, 8, OP_AC2D>(P, t0, a, b, c, grad, ws);
+  return adjoint_run<T, 8, OP_AC3D>(P, t0, a, b, c, grad, ws);
+}
+
+}  // namespace
+
+extern "C" int gbs_plan_adjoint_workspace_bytes(const gbs_plan* P, size_t* bytes) {
+  if (!P || !bytes) return fail(GBS_EINVAL, "null argument");
+  *bytes = adjoint_bytes(P);
+  return GBS_OK;
+}
+
+extern "C" int gbs_adjoint_step(gbs_plan* P, double t0, const void* y_in, void* ybar,
+                                const void* trace_bar, double* grad_c2, void* adj_ws,
+                                size_t adj_ws_bytes) {
+  if (!P || !y_in || !ybar || !adj_ws) return fail(GBS_EINVAL, "null argument");
+  if (P->prob.op == GBS_ADVECT1D) return fail(GBS_EUNSUPPORTED, "the adjoint is built for the acoustic operators");
+  if (grad_c2 && !P->prob.c2_field)
+    return fail(GBS_EINVAL, "a c^2 gradient needs a plan with a coefficient field");
+  if ((uintptr_t)adj_ws % kAlign) return fail(GBS_EINVAL, "adjoint workspace must be 256-byte aligned");
+  if (adj_ws_bytes < adjoint_bytes(P))
+    return fail(GBS_ENOMEM, "adjoint workspace has %zu bytes, needs %zu", adj_ws_bytes,
+                adjoint_bytes(P));
+  if (!std::isfinite(t0)) return fail(GBS_EINVAL, "t0 must be finite");
+  if (P->prob.dtype == GBS_F64)
+    return adjoint_dispatch<double>(P, t0, y_in, ybar, trace_bar, grad_c2, (char*)adj_ws);
+  return adjoint_dispatch<float>(P, t0, y_in, ybar, trace_bar, grad_c2, (char*)adj_ws);
 }

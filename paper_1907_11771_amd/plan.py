@@ -84,6 +84,50 @@ class GBSPlan:
                                              B._arr(ctypes.c_double, weight), float(f0),
                                              float(delay)))
 
+    def set_receivers(self, rhs, flat_index):
+        """Pressure receivers (right-hand side, index within one field)."""
+        self.n_rec = len(flat_index)
+        B.check(B.lib().gbs_plan_set_receivers(self.handle, self.n_rec,
+                                               B._arr(ctypes.c_int32, rhs),
+                                               B._arr(ctypes.c_int64, flat_index)))
+
+    def step_record(self, y, out=None, t0=0.0, n_macro=1, traces=None):
+        """As step(), also returning the receiver traces [n_macro, n_rec]."""
+        self._check_state(y)
+        if out is None:
+            out = torch.empty_like(y)
+        self._check_state(out)
+        n_rec = getattr(self, "n_rec", 0)
+        if traces is None:
+            traces = torch.empty((n_macro, max(n_rec, 1)), dtype=self.dtype, device=self.device)
+        B.check(B.lib().gbs_step_record(self.handle, float(t0), int(n_macro), y.data_ptr(),
+                                        out.data_ptr(), traces.data_ptr()))
+        return out, traces[:, :n_rec]
+
+    def adjoint_workspace(self):
+        if getattr(self, "_adj_ws", None) is None:
+            nb = ctypes.c_size_t()
+            B.check(B.lib().gbs_plan_adjoint_workspace_bytes(self.handle, ctypes.byref(nb)))
+            self._adj_ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
+        return self._adj_ws
+
+    def adjoint_step(self, t0, y_in, ybar, trace_bar=None, grad_c2=None):
+        """One macro step backwards: ybar (adjoint at t0 + H) is replaced by
+        the adjoint at t0; trace_bar [n_rec] is the adjoint of the traces
+        recorded at t0 + H; dL/dc^2 is added to grad_c2 (FP64)."""
+        self._check_state(y_in)
+        self._check_state(ybar)
+        if trace_bar is not None:
+            trace_bar = trace_bar.to(self.dtype).contiguous()
+        if grad_c2 is not None and (grad_c2.dtype != torch.float64 or not grad_c2.is_contiguous()):
+            raise ValueError("grad_c2 must be a contiguous float64 tensor")
+        ws = self.adjoint_workspace()
+        B.check(B.lib().gbs_adjoint_step(self.handle, float(t0), y_in.data_ptr(), ybar.data_ptr(),
+                                         trace_bar.data_ptr() if trace_bar is not None else None,
+                                         grad_c2.data_ptr() if grad_c2 is not None else None,
+                                         ws.data_ptr(), ws.numel()))
+        return ybar
+
     def set_variant(self, variant):
         B.check(B.lib().gbs_plan_set_variant(self.handle, int(variant)))
 

@@ -84,7 +84,7 @@ def test_workspace_bytes_formula():
     steps, w = _cfg2()
     nb = _plan(B.ACOUSTIC2D, (64, 32), 8, steps, w, 1e-3)
     pts = 64 * 32 * 3
-    assert nb == 512 + pts * 8 + 4 * 6 * pts * 8      # sources + acc + two pairs per sequence
+    assert nb == 512 + 16384 + pts * 8 + 4 * 6 * pts * 8   # sources, receivers, acc, pairs
 
 
 def test_plan_stability_limit_is_sharp():
