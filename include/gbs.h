@@ -188,6 +188,10 @@ int gbs_step(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void*
  *                           (one more row of time skew between levels)
  *   GBS_VARIANT_PLAIN       the unfused reference form: one streaming launch
  *                           per sequence per leap-frog step (every operator)
+ *   GBS_VARIANT_TEMPORAL_WG4/WG8  as GBS_VARIANT_TEMPORAL, with 4 / 8
+ *                           wavefronts of a workgroup sharing their edge
+ *                           columns through LDS (halo recomputed only at
+ *                           the workgroup's edges)
  * The temporally blocked variants agree with the streaming ones to
  * rounding (the combination is summed in the same order, the products may
  * be contracted differently).
@@ -206,7 +210,9 @@ enum {
   GBS_VARIANT_TEMPORAL4 = 7,
   GBS_VARIANT_TEMPORAL_S5 = 8,
   GBS_VARIANT_TEMPORAL_S6 = 9,
-  GBS_VARIANT_PLAIN = 10
+  GBS_VARIANT_PLAIN = 10,
+  GBS_VARIANT_TEMPORAL_WG4 = 11,
+  GBS_VARIANT_TEMPORAL_WG8 = 12
 };
 int gbs_plan_set_variant(gbs_plan* plan, int32_t variant);
 int gbs_plan_set_band(gbs_plan* plan, int32_t rows);

@@ -20,6 +20,7 @@ VARIANT_AUTO, VARIANT_FLAT, VARIANT_MARCH8, VARIANT_MARCH16 = 0, 1, 2, 3
 VARIANT_MARCH8_NT, VARIANT_MARCH16_NT = 4, 5
 VARIANT_TEMPORAL, VARIANT_TEMPORAL4, VARIANT_TEMPORAL_S5, VARIANT_TEMPORAL_S6 = 6, 7, 8, 9
 VARIANT_PLAIN = 10
+VARIANT_TEMPORAL_WG4, VARIANT_TEMPORAL_WG8 = 11, 12
 MAX_SEQ = 16
 MAX_SRC = 16
 MAX_REC = 1024

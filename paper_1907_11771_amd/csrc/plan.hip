@@ -219,9 +219,30 @@ int resolve_variant(const gbs_plan* P) {
   return GBS_VARIANT_FLAT;
 }
 
-bool is_temporal(int v) { return v >= GBS_VARIANT_TEMPORAL && v <= GBS_VARIANT_TEMPORAL_S6; }
+bool is_temporal(int v) {
+  return (v >= GBS_VARIANT_TEMPORAL && v <= GBS_VARIANT_TEMPORAL_S6) ||
+         v == GBS_VARIANT_TEMPORAL_WG4 || v == GBS_VARIANT_TEMPORAL_WG8;
+}
 
-template <typename T, int ORDER, int G, bool SKEW1>
+// Shape of a temporally blocked variant: at most G evaluations per pass,
+// time skew R (false) or R+1 (true), WPG wavefronts sharing edges.
+struct TemporalShape {
+  int G;
+  bool skew1;
+  int wpg;
+};
+TemporalShape temporal_shape(int v, int fd_order) {
+  const int wpg = v == GBS_VARIANT_TEMPORAL_WG4 ? 4 : v == GBS_VARIANT_TEMPORAL_WG8 ? 8 : 1;
+  if (fd_order == 8) return {3, true, wpg};
+  switch (v) {
+    case GBS_VARIANT_TEMPORAL4: return {4, false, 1};
+    case GBS_VARIANT_TEMPORAL_S5: return {5, true, 1};
+    case GBS_VARIANT_TEMPORAL_S6: return {6, true, 1};
+    default: return {7, false, wpg};
+  }
+}
+
+template <typename T, int ORDER, int G, bool SKEW1, int WPG>
 int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   constexpr int R = Fd<ORDER>::R;
   // split the N_j + 1 evaluations of every sequence into passes of at most G
@@ -274,7 +295,7 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         d.out_a = (T*)P->pair[j][q % 2][0];
         d.out_b = (T*)P->pair[j][q % 2][1];
         d.ystar = (double*)P->pair[j][q % 2][0];
-        d.strips = (nx + (64 - 2 * d.g * R) - 1) / (64 - 2 * d.g * R);
+        d.strips = (nx + (64 * WPG - 2 * d.g * R) - 1) / (64 * WPG - 2 * d.g * R);
         for (int e = 0; e < d.g; ++e)
           d.amp[e] = P->nsrc ? ricker(t + (s0 + e) * h, P->f0, P->delay) : 0.0;
         maxs = std::max(maxs, d.strips);
@@ -286,8 +307,9 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         ev = &next_event(P->lf_ev, P->lf_used);
         hipEventRecord(ev->a, P->stream);
       }
-      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1>), dim3((waves + 3) / 4, n, P->prob.n_rhs),
-                         dim3(256), 0, P->stream, pa);
+      const unsigned blocks = WPG > 1 ? waves : (waves + 3) / 4;
+      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG>), dim3(blocks, n, P->prob.n_rhs),
+                         dim3(WPG > 1 ? 64 * WPG : 256), 0, P->stream, pa);
       if (ev) hipEventRecord(ev->b, P->stream);
     }
     EventPair* ev = nullptr;
@@ -409,12 +431,18 @@ int dispatch_order(gbs_plan* P, double t0, int n, const void* yin, void* yout) {
   const int op = P->prob.op;
   const int v = resolve_variant(P);
   if (op == GBS_ACOUSTIC2D && is_temporal(v)) {
-    if (P->prob.fd_order == 8) return run_temporal<T, 8, 3, true>(P, t0, n, a, b);
+    if (P->prob.fd_order == 8) {
+      if (v == GBS_VARIANT_TEMPORAL_WG4) return run_temporal<T, 8, 3, true, 4>(P, t0, n, a, b);
+      if (v == GBS_VARIANT_TEMPORAL_WG8) return run_temporal<T, 8, 3, true, 8>(P, t0, n, a, b);
+      return run_temporal<T, 8, 3, true, 1>(P, t0, n, a, b);
+    }
     switch (v) {
-      case GBS_VARIANT_TEMPORAL4: return run_temporal<T, 4, 4, false>(P, t0, n, a, b);
-      case GBS_VARIANT_TEMPORAL_S5: return run_temporal<T, 4, 5, true>(P, t0, n, a, b);
-      case GBS_VARIANT_TEMPORAL_S6: return run_temporal<T, 4, 6, true>(P, t0, n, a, b);
-      default: return run_temporal<T, 4, 7, false>(P, t0, n, a, b);
+      case GBS_VARIANT_TEMPORAL4: return run_temporal<T, 4, 4, false, 1>(P, t0, n, a, b);
+      case GBS_VARIANT_TEMPORAL_S5: return run_temporal<T, 4, 5, true, 1>(P, t0, n, a, b);
+      case GBS_VARIANT_TEMPORAL_S6: return run_temporal<T, 4, 6, true, 1>(P, t0, n, a, b);
+      case GBS_VARIANT_TEMPORAL_WG4: return run_temporal<T, 4, 7, false, 4>(P, t0, n, a, b);
+      case GBS_VARIANT_TEMPORAL_WG8: return run_temporal<T, 4, 7, false, 8>(P, t0, n, a, b);
+      default: return run_temporal<T, 4, 7, false, 1>(P, t0, n, a, b);
     }
   }
   if (P->prob.fd_order == 4) {
@@ -543,7 +571,7 @@ extern "C" int gbs_step(gbs_plan* P, double t0, int32_t n_macro, const void* y_i
 
 extern "C" int gbs_plan_set_variant(gbs_plan* P, int32_t variant) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
-  if (variant < GBS_VARIANT_AUTO || variant > GBS_VARIANT_PLAIN)
+  if (variant < GBS_VARIANT_AUTO || variant > GBS_VARIANT_TEMPORAL_WG8)
     return fail(GBS_EINVAL, "unknown variant %d", variant);
   if (variant >= GBS_VARIANT_MARCH8 && variant != GBS_VARIANT_PLAIN && P->prob.op != GBS_ACOUSTIC2D)
     return fail(GBS_EUNSUPPORTED, "this variant is built for the 2-D acoustic operator only");
@@ -614,9 +642,7 @@ extern "C" int gbs_plan_algorithmic_bytes(const gbs_plan* P, double* step_bytes,
   double sb = 0, ab = 0;
   int64_t sl = 0, al = 0;
   if (P->prob.op == GBS_ACOUSTIC2D && is_temporal(v)) {
-    const int G = v == GBS_VARIANT_TEMPORAL4 ? 4 : v == GBS_VARIANT_TEMPORAL_S5 ? 5
-                : v == GBS_VARIANT_TEMPORAL_S6 ? 6 : (P->prob.fd_order == 8 ? 3 : 7);
-    const int Gx = P->prob.fd_order == 8 ? 3 : G;
+    const int Gx = temporal_shape(v, P->prob.fd_order).G;
     int maxpass = 0;
     for (int j = 0; j < P->k; ++j) {
       const int E = P->steps[j] + 1, np = (E + Gx - 1) / Gx;
@@ -706,15 +732,7 @@ struct gbs_batch_plan {
 
 namespace {
 
-int batch_gmax(int variant, int fd_order) {
-  if (fd_order == 8) return 3;
-  switch (variant) {
-    case GBS_VARIANT_TEMPORAL4: return 4;
-    case GBS_VARIANT_TEMPORAL_S5: return 5;
-    case GBS_VARIANT_TEMPORAL_S6: return 6;
-    default: return 7;
-  }
-}
+int batch_gmax(int variant, int fd_order) { return temporal_shape(variant, fd_order).G; }
 
 size_t batch_level_bytes(const gbs_problem& p) {
   return align_up((size_t)3 * p.n[0] * p.n[1] * dsize(p.dtype));
@@ -773,7 +791,7 @@ void batch_build_tables(gbs_batch_plan* B, void* const* y) {
         it.ny = ny;
         it.g = gsz[j][q];
         it.flags = (q == 0 ? PASS_FIRST : 0) | (q == npass[j] - 1 ? PASS_FINAL : 0);
-        const int wv = 64 - 2 * it.g * R;
+        const int wv = 64 * temporal_shape(B->variant, B->fd_order).wpg - 2 * it.g * R;
         it.strips = (nx + wv - 1) / wv;
         it.nbands = (ny + B->band - 1) / B->band;
         it.band = B->band;
@@ -813,17 +831,25 @@ void batch_launch_macro_step(gbs_batch_plan* B, hipStream_t s) {
     a.items = (const PassItem<T>*)(B->tab_dev + B->round_off[q]);
     a.n_items = B->round_items[q];
     a.total_waves = B->round_waves[q];
-    const dim3 grid((unsigned)((a.total_waves + 3) / 4));
+    const int wpg = temporal_shape(B->variant, B->fd_order).wpg;
+    const dim3 grid((unsigned)(wpg > 1 ? a.total_waves : (a.total_waves + 3) / 4));
+    const dim3 blk(wpg > 1 ? 64 * wpg : 256);
     if (B->fd_order == 8) {
-      hipLaunchKernelGGL((pass2d_batch<T, 8, 3, true>), grid, dim3(256), 0, s, a);
+      if (wpg == 4) hipLaunchKernelGGL((pass2d_batch<T, 8, 3, true, 4>), grid, blk, 0, s, a);
+      else if (wpg == 8) hipLaunchKernelGGL((pass2d_batch<T, 8, 3, true, 8>), grid, blk, 0, s, a);
+      else hipLaunchKernelGGL((pass2d_batch<T, 8, 3, true, 1>), grid, blk, 0, s, a);
+    } else if (wpg == 4) {
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 7, false, 4>), grid, blk, 0, s, a);
+    } else if (wpg == 8) {
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 7, false, 8>), grid, blk, 0, s, a);
     } else if (G == 4) {
-      hipLaunchKernelGGL((pass2d_batch<T, 4, 4, false>), grid, dim3(256), 0, s, a);
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 4, false, 1>), grid, blk, 0, s, a);
     } else if (G == 5) {
-      hipLaunchKernelGGL((pass2d_batch<T, 4, 5, true>), grid, dim3(256), 0, s, a);
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 5, true, 1>), grid, blk, 0, s, a);
     } else if (G == 6) {
-      hipLaunchKernelGGL((pass2d_batch<T, 4, 6, true>), grid, dim3(256), 0, s, a);
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 6, true, 1>), grid, blk, 0, s, a);
     } else {
-      hipLaunchKernelGGL((pass2d_batch<T, 4, 7, false>), grid, dim3(256), 0, s, a);
+      hipLaunchKernelGGL((pass2d_batch<T, 4, 7, false, 1>), grid, blk, 0, s, a);
     }
   }
   hipLaunchKernelGGL((combine_batch<T>), dim3((unsigned)B->comb_blocks), dim3(256), 0, s,
@@ -1018,7 +1044,8 @@ extern "C" int gbs_batch_step(gbs_batch_plan* B, int32_t n_macro, void* const* y
 extern "C" int gbs_batch_autotune(gbs_batch_plan* B, void* const* y, int32_t macro_steps,
                                   int32_t* variant_out, int32_t* band_out) {
   if (!B || !y || macro_steps < 1) return fail(GBS_EINVAL, "bad arguments");
-  const int variants[] = {GBS_VARIANT_TEMPORAL, GBS_VARIANT_TEMPORAL4, GBS_VARIANT_TEMPORAL_S5};
+  const int variants[] = {GBS_VARIANT_TEMPORAL, GBS_VARIANT_TEMPORAL4, GBS_VARIANT_TEMPORAL_S5,
+                          GBS_VARIANT_TEMPORAL_WG4, GBS_VARIANT_TEMPORAL_WG8};
   const int bands[] = {32, 64, 128};
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
@@ -1028,7 +1055,7 @@ extern "C" int gbs_batch_autotune(gbs_batch_plan* B, void* const* y, int32_t mac
   float best = 1e30f;
   int bv = B->variant, bb = B->band;
   for (int v : variants) {
-    if (B->fd_order == 8 && v != GBS_VARIANT_TEMPORAL) continue;
+    if (B->fd_order == 8 && (v == GBS_VARIANT_TEMPORAL4 || v == GBS_VARIANT_TEMPORAL_S5)) continue;
     for (int band : bands) {
       gbs_batch_set_variant(B, v, band);
       int st = gbs_batch_step(B, 1, y);                  // warm-up (and table upload)

@@ -116,7 +116,15 @@ struct PassWork {
   double amp[PASS_GMAX];
 };
 
-// One wavefront's pass over its strip and band.
+// A workgroup's pass over its strip and band.
+//
+// The workgroup's WPG wavefronts cover 64 * WPG consecutive columns; wave v
+// holds columns x0 - g R + 64 v + lane.  Inside a wavefront x-neighbours come
+// from adjacent lanes (DPP wave shifts); across wavefront boundaries the R
+// edge lanes of every level row are exchanged through a small LDS ring (the
+// value a level needs from its neighbour was produced S row steps earlier,
+// so one barrier per row step suffices).  Only the workgroup's outer g R
+// columns on each side are recomputed halo.
 //
 // Time skew between consecutive levels: with SKEW1 = false level e is
 // produced R rows behind level e-1 and the levels of one row step are
@@ -125,21 +133,54 @@ struct PassWork {
 // evaluated in descending order, so that all of them read only rows
 // produced in earlier row steps (independent work within a row step), at the
 // cost of one more window row per level.  The number of evaluations g of a
-// pass (at most G) is a runtime value, uniform over the wavefront.
-template <typename T, int ORDER, int G, bool SKEW1>
+// pass (at most G) is a runtime value, uniform over the workgroup.
+template <typename T, int R, int G, int S, int WPG>
+struct EdgeRing {
+  // [slot][wave][level][field p/vx][R left lanes, R right lanes]
+  T v[S + 1][WPG][G][2][2 * R];
+};
+
+// x-derivative sum with the lanes beyond this wavefront's edges supplied
+// by its neighbours' edge values (left: lanes 64-R..63, right: lanes 0..R-1).
+template <typename T, int ORDER>
+__device__ __forceinline__ T lane_dsum_edges(T u, int lane, const T* left, const T* right,
+                                             bool has_left, bool has_right) {
+  constexpr int R = Fd<ORDER>::R;
+  T up = lane_move<DPP_WAVE_SHL1>(u), dn = lane_move<DPP_WAVE_SHR1>(u);
+  if (has_right && lane == 63) up = right[0];
+  if (has_left && lane == 0) dn = left[R - 1];
+  T s = Fd<ORDER>::template w<T>(0) * (up - dn);
+#pragma unroll
+  for (int k = 1; k < R; ++k) {
+    up = lane_move<DPP_WAVE_SHL1>(up);
+    dn = lane_move<DPP_WAVE_SHR1>(dn);
+    if (has_right && lane == 63) up = right[k];
+    if (has_left && lane == 0) dn = left[R - 1 - k];
+    s += Fd<ORDER>::template w<T>(k) * (up - dn);
+  }
+  return s;
+}
+
+template <typename T, int ORDER, int G, bool SKEW1, int WPG>
 __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, const int band) {
   constexpr int R = Fd<ORDER>::R;
   constexpr int S = SKEW1 ? R + 1 : R;               // rows between consecutive levels
   constexpr int P = SKEW1 ? 2 * R + 2 : 2 * R + 1;   // window rows per level
+  __shared__ EdgeRing<T, R, G, S, WPG> ring;
   const int lane = threadIdx.x & 63;
+  const int wave = WPG > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
   const int nx = w.nx, ny = w.ny;
   const int g = w.g;
   const int halo = g * R;
-  const int wv = 64 - 2 * halo;
+  const int wv = 64 * WPG - 2 * halo;
   const int x0 = strip * wv;
-  const int col = x0 - halo + lane;                  // unwrapped column of this lane
+  const int col = x0 - halo + 64 * wave + lane;      // unwrapped column of this lane
   const int gx = pmod(col, nx);
-  const bool lane_ok = lane >= halo && lane < 64 - halo && col < nx;
+  const int gl = 64 * wave + lane;                   // lane within the workgroup
+  const bool lane_ok = gl >= halo && gl < 64 * WPG - halo && col < nx;
+  const bool has_left = WPG > 1 && wave > 0, has_right = WPG > 1 && wave < WPG - 1;
+  const bool edge_lane = lane < R || lane >= 64 - R;
+  const int edge_idx = lane < R ? lane : R + lane - (64 - R);
   const int ya = band * w.band;
   const int yb = min(ya + w.band, ny);
   const int i0 = ya - halo;                          // first input row (A_0)
@@ -166,6 +207,8 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const int k = kb + u;                          // row step; A_0 row i = i0 + k
+      // ring slots: written now, and produced S steps ago (read now)
+      const int wslot = k % (S + 1), rslot = (k + 1) % (S + 1);
       // input rows: A_0 at row i, and for a later pass A_{-1} at the row
       // level 1 updates in this step
       T nxt[3], om[3];
@@ -181,6 +224,12 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
           om[2] = old[e1 + F2];
         } else {
           om[0] = om[1] = om[2] = T(0);
+        }
+      }
+      if constexpr (WPG > 1) {
+        if (edge_lane) {
+          ring.v[wslot][wave][0][0][edge_idx] = nxt[0];
+          ring.v[wslot][wave][0][1][edge_idx] = nxt[1];
         }
       }
       if constexpr (!SKEW1) {
@@ -205,8 +254,19 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
           syp += Fd<ORDER>::template w<T>(kk) * (In[up][0] - In[dn][0]);
           syv += Fd<ORDER>::template w<T>(kk) * (In[up][2] - In[dn][2]);
         }
-        const T sxp = lane_dsum<T, ORDER>(In[c][0]);
-        const T sxv = lane_dsum<T, ORDER>(In[c][1]);
+        T sxp, sxv;
+        if constexpr (WPG > 1) {
+          // neighbours' edge values of level e-1's row i - e S (produced S
+          // row steps ago)
+          const int lw = has_left ? wave - 1 : wave, rw = has_right ? wave + 1 : wave;
+          sxp = lane_dsum_edges<T, ORDER>(In[c][0], lane, &ring.v[rslot][lw][e - 1][0][R],
+                                          &ring.v[rslot][rw][e - 1][0][0], has_left, has_right);
+          sxv = lane_dsum_edges<T, ORDER>(In[c][1], lane, &ring.v[rslot][lw][e - 1][1][R],
+                                          &ring.v[rslot][rw][e - 1][1][0], has_left, has_right);
+        } else {
+          sxp = lane_dsum<T, ORDER>(In[c][0]);
+          sxv = lane_dsum<T, ORDER>(In[c][1]);
+        }
         int row = 0;
         if (varc || srcs || e == g) row = wrap_sub(irow, e * S, ny);
         const int64_t pt = (int64_t)row * nx + gx;
@@ -253,6 +313,12 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
         } else if (e < G) {
 #pragma unroll
           for (int q = 0; q < 3; ++q) W[e][c][q] = nw[q];
+          if constexpr (WPG > 1) {
+            if (edge_lane) {
+              ring.v[wslot][wave][e][0][edge_idx] = nw[0];
+              ring.v[wslot][wave][e][1][edge_idx] = nw[1];
+            }
+          }
         }
       }
       if constexpr (SKEW1) {
@@ -260,18 +326,22 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
         for (int q = 0; q < 3; ++q) W[0][u][q] = nxt[q];
       }
       irow = irow + 1 == ny ? 0 : irow + 1;
+      if constexpr (WPG > 1) __syncthreads();
     }
   }
 }
 
 // One problem: blockIdx.y selects the sequence (its descriptor in the kernel
-// arguments), blockIdx.z the right-hand side.
-template <typename T, int ORDER, int G, bool SKEW1>
-__global__ __launch_bounds__(256) void pass2d(const PassArgs<T> a) {
+// arguments), blockIdx.z the right-hand side; a workgroup of WPG wavefronts
+// covers one (strip, band), or with WPG = 1 each wavefront of a 4-wave block
+// does.
+template <typename T, int ORDER, int G, bool SKEW1, int WPG>
+__global__ __launch_bounds__(WPG > 1 ? 64 * WPG : 256) void pass2d(const PassArgs<T> a) {
   const PassSeq<T>& d = a.seq[blockIdx.y];
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  const int strip = wave % a.max_strips;
-  const int band = wave / a.max_strips;
+  const int unit = WPG > 1 ? (int)blockIdx.x
+                           : __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int strip = unit % a.max_strips;
+  const int band = unit / a.max_strips;
   if (strip >= d.strips || band >= a.nbands) return;
   const int64_t base = (int64_t)blockIdx.z * a.g.state;
   PassWork<T> w;
@@ -296,12 +366,13 @@ __global__ __launch_bounds__(256) void pass2d(const PassArgs<T> a) {
   w.nsrc = a.g.nsrc;
 #pragma unroll
   for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = d.amp[e];
-  pass_body<T, ORDER, G, SKEW1>(w, strip, band);
+  pass_body<T, ORDER, G, SKEW1, WPG>(w, strip, band);
 }
 
 // A batch of problems: the passes of one round of every (instance, sequence)
-// are items of a device table; wave w belongs to the item whose first wave is
-// the largest wave_begin <= w.
+// are items of a device table; unit u (a wavefront, or a workgroup of WPG
+// wavefronts) belongs to the item whose first unit is the largest
+// unit_begin <= u.
 template <typename T>
 struct PassItem {
   const T* cur;
@@ -322,18 +393,19 @@ struct BatchPassArgs {
   int32_t total_waves;
 };
 
-template <typename T, int ORDER, int G, bool SKEW1>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void pass2d_batch(
-    const BatchPassArgs<T> a) {
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wave >= a.total_waves) return;
+template <typename T, int ORDER, int G, bool SKEW1, int WPG>
+__global__ __launch_bounds__(WPG > 1 ? 64 * WPG : 256) __attribute__((amdgpu_waves_per_eu(2)))
+void pass2d_batch(const BatchPassArgs<T> a) {
+  const int unit = WPG > 1 ? (int)blockIdx.x
+                           : __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (unit >= a.total_waves) return;
   int lo = 0, hi = a.n_items - 1;
-  while (lo < hi) {                                  // last item with wave_begin <= wave
+  while (lo < hi) {                                  // last item with wave_begin <= unit
     const int mid = (lo + hi + 1) >> 1;
-    if (a.items[mid].wave_begin <= wave) lo = mid; else hi = mid - 1;
+    if (a.items[mid].wave_begin <= unit) lo = mid; else hi = mid - 1;
   }
   const PassItem<T>* it = a.items + lo;
-  const int local = wave - it->wave_begin;
+  const int local = unit - it->wave_begin;
   const int strips = it->strips;
   PassWork<T> w;
   w.cur = it->cur;
@@ -357,7 +429,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void p
   w.nsrc = 0;
 #pragma unroll
   for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = 0.0;
-  pass_body<T, ORDER, G, SKEW1>(w, local % strips, local / strips);
+  pass_body<T, ORDER, G, SKEW1, WPG>(w, local % strips, local / strips);
 }
 
 // y_out = sum_j c_j y*_j, j in ascending N, accumulated in FP64.

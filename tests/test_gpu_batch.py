@@ -36,7 +36,8 @@ def _states(dtype, seed=0):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("variant,band", [(B.VARIANT_TEMPORAL, 64), (B.VARIANT_TEMPORAL4, 30),
-                                          (B.VARIANT_TEMPORAL_S5, 128)])
+                                          (B.VARIANT_TEMPORAL_S5, 128), (B.VARIANT_TEMPORAL_WG4, 64),
+                                          (B.VARIANT_TEMPORAL_WG8, 48)])
 def test_batch_equals_single_instances(dtype, variant, band):
     sch = schemes.ORDER8_K6
     steps, w, _ = scheme_weights(sch)
@@ -95,7 +96,8 @@ def test_batch_autotune_picks_a_candidate():
     inst = _instances(torch.float64)
     batch = GBSBatch(inst, 8, steps, w)
     v, band = batch.autotune(_states(torch.float64), macro_steps=1)
-    assert v in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5)
+    assert v in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
+                 B.VARIANT_TEMPORAL_WG4, B.VARIANT_TEMPORAL_WG8)
     assert band in (32, 64, 128)
     ys = _states(torch.float64, seed=3)
     ref = [y.clone() for y in ys]

@@ -138,7 +138,9 @@ def test_kernel_variants_agree_bitwise(dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("variant,band", [(B.VARIANT_TEMPORAL, 128), (B.VARIANT_TEMPORAL, 7),
                                           (B.VARIANT_TEMPORAL4, 50), (B.VARIANT_TEMPORAL, 1000),
-                                          (B.VARIANT_TEMPORAL_S5, 64), (B.VARIANT_TEMPORAL_S6, 33)])
+                                          (B.VARIANT_TEMPORAL_S5, 64), (B.VARIANT_TEMPORAL_S6, 33),
+                                          (B.VARIANT_TEMPORAL_WG4, 64), (B.VARIANT_TEMPORAL_WG8, 20),
+                                          (B.VARIANT_TEMPORAL_WG8, 128)])
 def test_temporal_passes_match_streaming(dtype, variant, band):
     # temporally blocked passes against the streaming sweeps: same values up
     # to the contraction of products (and FP32 rounding of the levels)
@@ -162,14 +164,16 @@ def test_temporal_passes_match_streaming(dtype, variant, band):
     assert rel_err(res[1], res[0]) <= tol
 
 
-def test_temporal_fd8_matches_oracle():
+@pytest.mark.parametrize("variant", [B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL_WG4,
+                                     B.VARIANT_TEMPORAL_WG8])
+def test_temporal_fd8_matches_oracle(variant):
     ny, nx = 48, 70
     sch = schemes.ORDER8_K6
     steps, c = oracle_weights(sch)
     H = workloads.stable_H(workloads.ISB_ORDER8_K6, 1.0, 1.0 / nx, 2, workloads.SIGMA_FD8)
     y0 = np.random.default_rng(4).standard_normal((3, ny, nx))
     plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, fd_order=8, check_stability=False)
-    plan.set_variant(B.VARIANT_TEMPORAL)
+    plan.set_variant(variant)
     got = plan.step(to_dev(y0[None]), n_macro=3).cpu().numpy()[0]
     want = G.integrate(OP.Acoustic((ny, nx), c2=1.0, r=4), 0.0, y0, H, 3, steps, c)
     assert rel_err(got, want) <= TOL64
