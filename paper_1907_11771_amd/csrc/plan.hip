@@ -242,20 +242,63 @@ TemporalShape temporal_shape(int v, int fd_order) {
   }
 }
 
+// Passes of every sequence: the N_j + 1 evaluations split into
+// ceil((N_j+1)/G) passes of near-equal size; a sequence's pass q runs in
+// round round0[j] + q.  Sequences with several passes start in round 0.
+// With balance = true single-pass sequences go to the round with the least
+// work so far (work of a pass ~ g times its halo overhead
+// 64 wpg / (64 wpg - 2 g R)); otherwise they run in round 0, which measured
+// faster on the 2048^2 workload (the first round's extra waves fill the GPU
+// better than an even split).
+struct PassSchedule {
+  int npass[GBS_MAX_SEQ];
+  int gsz[GBS_MAX_SEQ][32];
+  int round0[GBS_MAX_SEQ];
+  int nrounds = 0;
+};
+
+int make_schedule(const int32_t* steps, int k, int G, int R, int wpg, PassSchedule& s,
+                  bool balance = false) {
+  double work[64] = {0};
+  s.nrounds = 0;
+  auto cost = [&](int g) { return g * (64.0 * wpg) / (64.0 * wpg - 2.0 * g * R); };
+  for (int j = 0; j < k; ++j) {
+    const int E = steps[j] + 1;
+    const int np = (E + G - 1) / G;
+    if (np > 32) return fail(GBS_EUNSUPPORTED, "too many passes per sequence");
+    s.npass[j] = np;
+    for (int q = 0; q < np; ++q) s.gsz[j][q] = E / np + (q < E % np ? 1 : 0);
+    s.nrounds = std::max(s.nrounds, np);
+  }
+  for (int j = 0; j < k; ++j) {
+    if (s.npass[j] > 1) {
+      s.round0[j] = 0;
+      for (int q = 0; q < s.npass[j]; ++q) work[q] += cost(s.gsz[j][q]);
+    }
+  }
+  // single-pass sequences, largest first
+  int ord[GBS_MAX_SEQ], n1 = 0;
+  for (int j = 0; j < k; ++j)
+    if (s.npass[j] == 1) ord[n1++] = j;
+  std::sort(ord, ord + n1, [&](int a, int b) { return s.gsz[a][0] > s.gsz[b][0]; });
+  for (int t = 0; t < n1; ++t) {
+    const int j = ord[t];
+    int best = 0;
+    for (int r = 1; balance && r < s.nrounds; ++r)
+      if (work[r] < work[best]) best = r;
+    s.round0[j] = best;
+    work[best] += cost(s.gsz[j][0]);
+  }
+  return GBS_OK;
+}
+
 template <typename T, int ORDER, int G, bool SKEW1, int WPG>
 int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   constexpr int R = Fd<ORDER>::R;
-  // split the N_j + 1 evaluations of every sequence into passes of at most G
-  int npass[GBS_MAX_SEQ], gsz[GBS_MAX_SEQ][32];
-  int maxpass = 0;
-  for (int j = 0; j < P->k; ++j) {
-    const int E = P->steps[j] + 1;
-    const int np = (E + G - 1) / G;
-    if (np > 32) return fail(GBS_EUNSUPPORTED, "too many passes");
-    npass[j] = np;
-    for (int q = 0; q < np; ++q) gsz[j][q] = E / np + (q < E % np ? 1 : 0);
-    maxpass = std::max(maxpass, np);
-  }
+  PassSchedule sch;
+  int st = make_schedule(P->steps, P->k, G, R, WPG, sch);
+  if (st) return st;
+  const int* npass = sch.npass;
   PassArgs<T> pa;
   std::memset(&pa, 0, sizeof(pa));
   T c2c, invz;
@@ -278,16 +321,17 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   for (int m = 0; m < n_macro; ++m) {
     const double t = t0 + m * P->H;
     const T* y0 = m == 0 ? yin : yout;
-    for (int q = 0; q < maxpass; ++q) {
+    for (int rr = 0; rr < sch.nrounds; ++rr) {
       int n = 0, maxs = 0;
       for (int r = 0; r < P->k; ++r) {
         const int j = P->order[r];
-        if (q >= npass[j]) continue;
+        const int q = rr - sch.round0[j];
+        if (q < 0 || q >= npass[j]) continue;
         PassSeq<T>& d = pa.seq[n++];
         const double h = P->H / P->steps[j];
         int s0 = 0;             // the pass's input level is y_{s0}: s0 = evaluations so far
-        for (int qq = 0; qq < q; ++qq) s0 += gsz[j][qq];
-        d.g = gsz[j][q];
+        for (int qq = 0; qq < q; ++qq) s0 += sch.gsz[j][qq];
+        d.g = sch.gsz[j][q];
         d.h = (T)h;
         d.flags = (q == 0 ? PASS_FIRST : 0) | (q == npass[j] - 1 ? PASS_FINAL : 0);
         d.cur = q == 0 ? y0 : (const T*)P->pair[j][(q - 1) % 2][1];
@@ -751,13 +795,11 @@ template <typename T>
 void batch_build_tables(gbs_batch_plan* B, void* const* y) {
   const int G = batch_gmax(B->variant, B->fd_order);
   const int R = B->fd_order / 2;
-  int npass[GBS_MAX_SEQ], gsz[GBS_MAX_SEQ][32], maxpass = 0;
-  for (int j = 0; j < B->k; ++j) {
-    const int E = B->steps[j] + 1, np = (E + G - 1) / G;
-    npass[j] = np;
-    for (int q = 0; q < np; ++q) gsz[j][q] = E / np + (q < E % np ? 1 : 0);
-    maxpass = std::max(maxpass, np);
-  }
+  const int wpg = temporal_shape(B->variant, B->fd_order).wpg;
+  PassSchedule sch;
+  make_schedule(B->steps, B->k, G, R, wpg, sch);
+  const int* npass = sch.npass;
+  const int maxpass = sch.nrounds;
   B->tab_host.assign(B->tab_bytes, 0);
   B->round_off.assign(maxpass, 0);
   B->round_items.assign(maxpass, 0);
@@ -772,14 +814,16 @@ void batch_build_tables(gbs_batch_plan* B, void* const* y) {
       const int nx = (int)p.n[0], ny = (int)p.n[1];
       for (int r = 0; r < B->k; ++r) {
         const int j = B->order[r];
-        if (q >= npass[j]) continue;
+        const int rq = q;                               // round
+        const int qp = rq - sch.round0[j];              // this sequence's pass in the round
+        if (qp < 0 || qp >= npass[j]) continue;
         PassItem<T>& it = items[m++];
         auto& pr = B->pair[i][j];
-        it.cur = q == 0 ? (const T*)y[i] : (const T*)pr[(q - 1) % 2][1];
-        it.old = q == 0 ? nullptr : (const T*)pr[(q - 1) % 2][0];
-        it.out_a = (T*)pr[q % 2][0];
-        it.out_b = (T*)pr[q % 2][1];
-        it.ystar = (double*)pr[q % 2][0];
+        it.cur = qp == 0 ? (const T*)y[i] : (const T*)pr[(qp - 1) % 2][1];
+        it.old = qp == 0 ? nullptr : (const T*)pr[(qp - 1) % 2][0];
+        it.out_a = (T*)pr[qp % 2][0];
+        it.out_b = (T*)pr[qp % 2][1];
+        it.ystar = (double*)pr[qp % 2][0];
         it.c2f = (const T*)p.c2_field;
         it.field = (int64_t)nx * ny;
         it.h = (T)(B->H[i] / B->steps[j]);
@@ -789,8 +833,8 @@ void batch_build_tables(gbs_batch_plan* B, void* const* y) {
         it.invy = (T)((double)ny / den);
         it.nx = nx;
         it.ny = ny;
-        it.g = gsz[j][q];
-        it.flags = (q == 0 ? PASS_FIRST : 0) | (q == npass[j] - 1 ? PASS_FINAL : 0);
+        it.g = sch.gsz[j][qp];
+        it.flags = (qp == 0 ? PASS_FIRST : 0) | (qp == npass[j] - 1 ? PASS_FINAL : 0);
         const int wv = 64 * temporal_shape(B->variant, B->fd_order).wpg - 2 * it.g * R;
         it.strips = (nx + wv - 1) / wv;
         it.nbands = (ny + B->band - 1) / B->band;
