@@ -22,18 +22,16 @@ STREAM_BYTES_PER_UPDATE = 72.0   # FP64 2-D acoustic leap-frog update, streaming
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
 # the plain-copy calibration) for the kernel as it is now; see profiles/.  An
 # entry must be removed when its kernel changes.
-MEASURED_TRAFFIC_BYTES_PER_LAUNCH = {
-    "gbs::pass2d<double, 4, 7, false, 1>": 1.605e9,   # profiles/pass2d_acoustic2d_2048_fd4_f64.txt
-}
+MEASURED_TRAFFIC_BYTES_PER_LAUNCH = {}
 
 
 def kernel_names(variant, B):
-    step = {B.VARIANT_TEMPORAL: "gbs::pass2d<double, 4, 7, false, 1>",
-            B.VARIANT_TEMPORAL4: "gbs::pass2d<double, 4, 4, false, 1>",
-            B.VARIANT_TEMPORAL_S5: "gbs::pass2d<double, 4, 5, true, 1>",
-            B.VARIANT_TEMPORAL_S6: "gbs::pass2d<double, 4, 6, true, 1>",
-            B.VARIANT_TEMPORAL_WG4: "gbs::pass2d<double, 4, 7, false, 4>",
-            B.VARIANT_TEMPORAL_WG8: "gbs::pass2d<double, 4, 7, false, 8>",
+    step = {B.VARIANT_TEMPORAL: "gbs::pass2d<double, 4, 7, false, 1, false>",
+            B.VARIANT_TEMPORAL4: "gbs::pass2d<double, 4, 4, false, 1, false>",
+            B.VARIANT_TEMPORAL_S5: "gbs::pass2d<double, 4, 5, true, 1, false>",
+            B.VARIANT_TEMPORAL_S6: "gbs::pass2d<double, 4, 6, true, 1, false>",
+            B.VARIANT_TEMPORAL_WG4: "gbs::pass2d<double, 4, 7, false, 4, false>",
+            B.VARIANT_TEMPORAL_WG8: "gbs::pass2d<double, 4, 7, false, 8, false>",
             B.VARIANT_FLAT: "gbs::lf_kernel<double, 4, 2>"}.get(variant,
                                                               "gbs::lf_march2d<double, 4, ...>")
     temporal = variant in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
@@ -137,6 +135,226 @@ def bench_batch(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_adjoint(args):
+    """Forward + checkpointed adjoint of the receiver misfit (gradients with
+    respect to c^2 and p(0)) on the 1024^2 workload: FP64 blocked forward,
+    FP32 stepping, and the plain FP64 form; the FP32 gradient's error is
+    stated against the FP64 one."""
+    import numpy as np
+    import torch
+    from paper_1907_11771_amd import binding as B
+    from paper_1907_11771_amd.autograd import receiver_traces
+    from paper_1907_11771_amd.plan import GBSPlan, scheme_weights
+    from synth import fields, workloads
+
+    cfg = workloads.CONFIG_ADJOINT
+    n, nm = cfg["n"], cfg["n_macro"] if args.steps == 500 else args.steps
+    steps, w, _ = scheme_weights(cfg["scheme"])
+    dev = torch.device("cuda:0")
+    cs = fields.lognormal_speed((n, n), seed=cfg["speed_seed"])
+    c2 = cs ** 2
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / n, 2, workloads.SIGMA_FD4)
+    s = fields.ricker_source_2d(n)
+    rec = fields.edge_receivers_2d(n, count=cfg["receivers"])
+    c2_obs = c2 * np.exp(0.1 * fields.gaussian_random_field((n, n), seed=cfg["data_seed"]))
+
+    def make(dtype, variant=0):
+        pl = GBSPlan(B.ACOUSTIC2D, (n, n), 8, steps, w, H, dtype=dtype,
+                     c2_field=torch.from_numpy(c2).to(dev), c_max=float(cs.max()) * 1.01,
+                     device=dev)
+        if variant:
+            pl.set_variant(variant)
+        else:
+            pl.autotune(torch.zeros(pl.state_shape, dtype=dtype, device=dev), macro_steps=3)
+        pl.set_sources([0], [s["idx"][0] * n + s["idx"][1]], [s["weight"]], s["f0"], s["delay"])
+        pl.set_receivers([0] * len(rec), [int(r[0]) * n + int(r[1]) for r in rec])
+        return pl
+
+    ref = make(torch.float64)
+    with torch.no_grad():
+        data = receiver_traces(ref, torch.zeros((1, 3, n, n), dtype=torch.float64, device=dev),
+                               torch.from_numpy(c2_obs).to(dev), nm)
+
+    def run(pl, dtype):
+        y0 = torch.zeros((1, 3, n, n), dtype=dtype, device=dev, requires_grad=True)
+        c2v = torch.from_numpy(c2).to(dev, dtype).requires_grad_(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tr = receiver_traces(pl, y0, c2v, nm, checkpoint_every=cfg["checkpoint_every"])
+        loss = 0.5 * ((tr.double() - data) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t, t2 - t1, c2v.grad.double(), float(loss.detach())
+
+    def warm(pl, dtype):
+        y0 = torch.zeros((1, 3, n, n), dtype=dtype, device=dev, requires_grad=True)
+        c2v = torch.from_numpy(c2).to(dev, dtype).requires_grad_(True)
+        tr = receiver_traces(pl, y0, c2v, 4, checkpoint_every=2)
+        tr.sum().backward()
+        torch.cuda.synchronize()
+
+    forms = {"f64": (torch.float64, 0), "f32": (torch.float32, 0),
+             "plain": (torch.float64, B.VARIANT_PLAIN)}
+    plans = {k: make(dt, v) for k, (dt, v) in forms.items()}
+    for k, (dt, _) in forms.items():
+        warm(plans[k], dt)
+    f64, b64, g64, l64 = run(plans["f64"], torch.float64)
+    f32, b32, g32, l32 = run(plans["f32"], torch.float32)
+    fpl, bpl, gpl, _ = run(plans["plain"], torch.float64)
+    tuned = {k: plans[k].variant() for k in ("f64", "f32")}
+    rel = lambda a, b: float((a - b).norm() / b.norm())
+    upd = n * n * (1 + sum(steps)) * nm
+    rec_out = dict(
+        metric="fwd+adjoint time at fixed error vs plain", value=(f64 + b64), unit="s",
+        higher_is_better=False, n_gpus=1, steps=nm, warmup=1, dtype="f64", data="synthetic",
+        config=dict(workload=cfg["name"], grid=[n, n], macro_steps=nm,
+                    checkpoint_every=cfg["checkpoint_every"], receivers=len(rec)),
+        fp64=dict(forward_s=f64, adjoint_s=b64, forward_updates_per_s=upd / f64),
+        fp32_stepping=dict(forward_s=f32, adjoint_s=b32,
+                           grad_c2_rel_err_vs_fp64=rel(g32, g64),
+                           misfit_rel_err_vs_fp64=abs(l32 - l64) / abs(l64)),
+        plain_fp64=dict(forward_s=fpl, adjoint_s=bpl, grad_c2_rel_diff_vs_fp64=rel(gpl, g64)),
+        speedup_vs_plain=dict(fp64=(fpl + bpl) / (f64 + b64), fp32=(fpl + bpl) / (f32 + b32)),
+        forward_variant=tuned,
+    )
+    print(json.dumps(rec_out), flush=True)
+
+
+def bench_3d(args):
+    """384^3 FD8 acoustic, 8 right-hand sides (one Ricker point source each).
+    Forward: FP32 stepping with the FP64 combination over all 8 right-hand
+    sides in one plan, and the same steps in FP64 for the error statement.
+    Gradient: receiver misfit against data from a perturbed c^2 (FP64, all
+    8 right-hand sides), forward + checkpointed adjoint in FP32 stepping,
+    run in groups of right-hand sides so that checkpoints, recomputed
+    states and the adjoint's levels fit in HBM; the FP32 gradient of the
+    first group is compared with the FP64 one."""
+    import numpy as np
+    import torch
+    from paper_1907_11771_amd import binding as B
+    from paper_1907_11771_amd.autograd import receiver_traces
+    from paper_1907_11771_amd.plan import GBSPlan, scheme_weights
+    from synth import fields, workloads
+
+    cfg = workloads.CONFIG_3D
+    n, R = cfg["n"], cfg["n_rhs"]
+    nm = cfg["n_macro"] if args.steps == 500 else args.steps
+    ck = cfg["checkpoint_every"]
+    steps, w, _ = scheme_weights(cfg["scheme"])
+    dev = torch.device("cuda:0")
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    cs = fields.bandlimited_lognormal_speed(n, seed=cfg["speed_seed"], kmax=cfg["kmax"])
+    c2 = cs * cs
+    g_obs = np.log(fields.bandlimited_lognormal_speed(n, seed=cfg["data_seed"],
+                                                      kmax=cfg["kmax"], sigma=1.0))
+    c2_obs = c2 * np.exp(0.1 * g_obs)
+    del g_obs
+    c_top = float(np.sqrt(max(c2.max(), c2_obs.max())))
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, c_top, 1.0 / n, 3, workloads.SIGMA_FD8)
+    src = fields.ricker_source_3d(n, workloads.sources_3d(n, R, cfg["source_seed"]))
+    rec = fields.plane_receivers_3d(n, cfg["receivers"])
+    log("acoustic3d: fields ready, H = %.6g" % H)
+
+    def make(dtype, rhs, c2_host, receivers=False):
+        pl = GBSPlan(B.ACOUSTIC3D, (n, n, n), 8, steps, w, H, fd_order=8, n_rhs=len(rhs),
+                     dtype=dtype, c2_field=torch.from_numpy(c2_host).to(dev), c_max=c_top,
+                     device=dev)
+        pts = [src["points"][r] for r in rhs]
+        pl.set_sources(list(range(len(rhs))), [z * n * n + y * n + x for z, y, x in pts],
+                       [src["weight"]] * len(rhs), src["f0"], src["delay"])
+        if receivers:
+            pl.set_receivers([i for i in range(len(rhs)) for _ in rec],
+                             [z * n * n + y * n + x for _ in rhs for z, y, x in rec])
+        return pl
+
+    def release():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+    # forward throughput, all right-hand sides in one plan
+    res, finals = {}, {}
+    for dtype in (torch.float32, torch.float64):
+        pl = make(dtype, range(R), c2)
+        y = torch.zeros((R, 4, n, n, n), dtype=dtype, device=dev)
+        pl.step(y, y, n_macro=1)
+        y.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pl.step(y, y, n_macro=nm)
+        torch.cuda.synchronize()
+        res[dtype] = time.perf_counter() - t
+        finals[dtype] = y[:, 0].cpu().double()
+        log("acoustic3d forward %s: %.3f s for %d macro steps" % (dtype, res[dtype], nm))
+        del pl, y
+        release()
+    t32 = res[torch.float32]
+    fwd_err = float((finals[torch.float32] - finals[torch.float64]).abs().max()
+                    / finals[torch.float64].abs().max())
+    del finals
+
+    # data: receiver traces of the perturbed model, FP64, all right-hand sides
+    parts = []
+    for s0 in range(0, R, 4):
+        pl = make(torch.float64, range(s0, s0 + 4), c2_obs, receivers=True)
+        with torch.no_grad():
+            y0 = torch.zeros((4, 4, n, n, n), dtype=torch.float64, device=dev)
+            parts.append(receiver_traces(pl, y0, pl.c2_field, nm, checkpoint_every=nm))
+        del pl, y0
+        release()
+    data = torch.cat(parts, dim=1)
+    nrec = len(rec)
+    log("acoustic3d: data ready")
+
+    def gradient(dtype, rhs):
+        pl = make(dtype, rhs, c2, receivers=True)
+        y0 = torch.zeros((len(rhs), 4, n, n, n), dtype=dtype, device=dev, requires_grad=True)
+        c2v = torch.from_numpy(c2).to(dev, dtype).requires_grad_(True)
+        d = data[:, [r * nrec + i for r in rhs for i in range(nrec)]]
+        d = d.contiguous()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tr = receiver_traces(pl, y0, c2v, nm, checkpoint_every=ck)
+        loss = 0.5 * ((tr.double() - d) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g = c2v.grad.double().clone()
+        del pl, y0, c2v, tr
+        release()
+        log("acoustic3d gradient %s rhs %s: forward %.2f s, adjoint %.2f s"
+            % (dtype, list(rhs), t1 - t, t2 - t1))
+        return t1 - t, t2 - t1, g, float(loss.detach())
+
+    group = 1
+    fw = bw = 0.0
+    g32_first = None
+    for s0 in range(0, R, group):
+        a, b_, g, _ = gradient(torch.float32, list(range(s0, s0 + group)))
+        fw, bw = fw + a, bw + b_
+        if s0 == 0:
+            g32_first = g
+        del g
+    a64, b64, g64, _ = gradient(torch.float64, list(range(group)))
+    grad_err = float((g32_first - g64).norm() / g64.norm())
+    upd = n ** 3 * R * (1 + sum(steps)) * nm
+    print(json.dumps(dict(
+        metric="grid-pt RHS updates/s", value=upd / t32, unit="grid-pt RHS updates/s",
+        n_gpus=1, steps=nm, warmup=1, ms_per_step=t32 * 1e3 / nm, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload=cfg["name"], grid=[n, n, n], n_rhs=R, fd_order=8),
+        fp64_ms_per_step=res[torch.float64] * 1e3 / nm,
+        fp32_max_rel_err_vs_fp64_pressure=fwd_err,
+        gradient=dict(receivers_per_rhs=nrec, checkpoint_every=ck, rhs_per_group=group,
+                      fp32_forward_s=fw, fp32_adjoint_s=bw,
+                      fp64_forward_s_first_group=a64, fp64_adjoint_s_first_group=b64,
+                      grad_c2_rel_err_fp32_vs_fp64_first_group=grad_err))), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,9 +366,11 @@ def main():
     ap.add_argument("--band", type=int, default=0,
                     help="rows per band of the temporally blocked passes (0 = default)")
     ap.add_argument("--workload", default="acoustic2d",
-                    choices=["acoustic2d", "batch64"],
+                    choices=["acoustic2d", "batch64", "adjoint1024", "acoustic3d"],
                     help="acoustic2d: the 2048^2 FP64 workload (default); batch64: 64 "
-                         "uneven instances in one batch")
+                         "uneven instances in one batch; adjoint1024: forward + adjoint "
+                         "gradient of the 1024^2 receiver misfit; acoustic3d: 384^3 FD8, "
+                         "8 right-hand sides")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"],
                     help="stepping precision of the batch workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -179,6 +399,10 @@ def main():
 
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "adjoint1024":
+        return bench_adjoint(args)
+    if args.workload == "acoustic3d":
+        return bench_3d(args)
 
     cfg = workloads.CONFIG_ACOUSTIC2D
     n = cfg["n"]

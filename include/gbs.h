@@ -175,8 +175,10 @@ int gbs_step(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void*
  * the same values in the same order; they differ in work layout only):
  *   GBS_VARIANT_AUTO        library's choice (default)
  *   GBS_VARIANT_FLAT        one grid point per thread (every operator)
- *   GBS_VARIANT_MARCH8/16   2-D acoustic only: each thread marches 8 / 16
- *                           rows, y-stencil rows kept in registers
+ *   GBS_VARIANT_MARCH8/16   2-D acoustic: each thread marches 8 / 16 rows,
+ *                           y-stencil rows kept in registers; 3-D acoustic:
+ *                           each thread marches 64 / 128 planes, z-stencil
+ *                           planes kept in registers (3-D default: MARCH8)
  *   GBS_VARIANT_MARCH8/16_NT  as above with non-temporal level stores
  *   GBS_VARIANT_TEMPORAL    2-D acoustic only: temporally blocked passes of
  *                           up to 7 (FD4) / 3 (FD8) evaluations of f per
@@ -217,6 +219,18 @@ enum {
 int gbs_plan_set_variant(gbs_plan* plan, int32_t variant);
 int gbs_plan_set_band(gbs_plan* plan, int32_t rows);
 int gbs_plan_get_variant(const gbs_plan* plan, int32_t* variant);
+
+/*
+ * gbs_plan_autotune — the project's own tuner: times every temporally
+ * blocked variant (those built for the plan's stencil order) at 32, 64 and
+ * 128 rows per band, macro_steps macro steps each from y_in into y_out
+ * (device buffers of one state, may be the same; y_out is overwritten), on
+ * the plan's stream, and keeps the fastest.  Operators other than the 2-D
+ * acoustic one have a single form: the call returns it unchanged.
+ * variant_out and band_out are nullable.  Synchronises the plan's stream.
+ */
+int gbs_plan_autotune(gbs_plan* plan, const void* y_in, void* y_out, int32_t macro_steps,
+                      int32_t* variant_out, int32_t* band_out);
 
 /*
  * gbs_plan_set_timing — enabled != 0: every kernel launch is bracketed by HIP

@@ -23,16 +23,18 @@ class _ReceiverTraces(torch.autograd.Function):
         plan.c2_field.copy_(c2.detach().to(plan.c2_field.dtype))
         y = y0.detach().to(plan.dtype).contiguous().clone()
         cps = {0: y.clone()}
-        rows = []
-        for m in range(n_macro):
-            _, tr = plan.step_record(y, y, t0=t0 + m * plan.H, n_macro=1)
-            rows.append(tr[0].clone())
-            if (m + 1) % checkpoint_every == 0 and m + 1 < n_macro:
-                cps[m + 1] = y.clone()
+        traces = torch.empty((n_macro, max(getattr(plan, "n_rec", 0), 1)), dtype=plan.dtype,
+                             device=plan.device)
+        # one library call per checkpoint segment
+        for s in range(0, n_macro, checkpoint_every):
+            e = min(s + checkpoint_every, n_macro)
+            plan.step_record(y, y, t0=t0 + s * plan.H, n_macro=e - s, traces=traces[s:e])
+            if e < n_macro:
+                cps[e] = y.clone()
         ctx.plan, ctx.n_macro, ctx.t0, ctx.ck = plan, n_macro, t0, checkpoint_every
         ctx.cps = cps
         ctx.y0_dtype, ctx.c2_dtype = y0.dtype, c2.dtype
-        return torch.stack(rows).to(y0.dtype)
+        return traces[:, :getattr(plan, "n_rec", 0)].to(y0.dtype)
 
     @staticmethod
     def backward(ctx, gtr):

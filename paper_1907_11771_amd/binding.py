@@ -77,12 +77,13 @@ def lib():
             "gbs_plan_set_timing": [vp, i32],
             "gbs_plan_set_variant": [vp, i32],
             "gbs_plan_get_variant": [vp, P(i32)],
+            "gbs_plan_autotune": [vp, vp, vp, i32, P(i32), P(i32)],
             "gbs_plan_set_band": [vp, i32],
             "gbs_plan_get_timing": [vp, P(dbl), P(i64), P(dbl), P(i64)],
             "gbs_plan_updates_per_macro_step": [vp, P(dbl)],
             "gbs_plan_algorithmic_bytes": [vp, P(dbl), P(i64), P(dbl), P(i64)],
             "gbs_plan_destroy": [vp],
-"gbs_plan_set_receivers": [vp, i32, P(i32), P(i64)],
+            "gbs_plan_set_receivers": [vp, i32, P(i32), P(i64)],
             "gbs_step_record": [vp, dbl, i32, vp, vp, vp],
             "gbs_plan_adjoint_workspace_bytes": [vp, P(sz)],
             "gbs_adjoint_step": [vp, dbl, vp, vp, vp, vp, vp, sz],

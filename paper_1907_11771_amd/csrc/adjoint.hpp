@@ -173,6 +173,123 @@ __global__ __launch_bounds__(256) void adj_lf_kernel(const AdjArgs<T> a) {
   if (a.grad) a.grad[idx] += gsum;
 }
 
+// The two sweeps above for the 3-D operator, marching in z (the layout of
+// lf_march3d): each thread walks up its (x, y) column keeping the planes
+// z-R..z+R of c^2 u_p, u_vz and the level's v_z in registers, while the x-
+// and y-derivatives read the current plane.  FIRST: u = ybar (step n = N),
+// else u = P.  The right-hand sides are looped over inside the thread, so
+// the c^2 gradient of a point has one writer.  Same products and sums, in
+// the same order, as adj_first_kernel / adj_lf_kernel (the gradient adds
+// the right-hand sides' terms one at a time).
+template <typename T, int ORDER, int TZ, bool FIRST>
+__global__ __launch_bounds__(256) void adj_march3d(const AdjArgs<T> a) {
+  constexpr int R = Fd<ORDER>::R;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int ntx = (nx + 63) >> 6, nty = (ny + 3) >> 2;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx;
+  const int ty = (tile / ntx) % nty;
+  const int tz = tile / (ntx * nty);
+  const int x = tx * 64 + (threadIdx.x & 63);
+  const int y = ty * 4 + (threadIdx.x >> 6);
+  const int z0 = tz * TZ;
+  if (x >= nx || y >= ny || z0 >= nz) return;
+  const int64_t F1 = a.g.field, F2 = 2 * a.g.field, F3 = 3 * a.g.field;
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t pil = (int64_t)y * nx + x;
+  const int zend = min(z0 + TZ, nz);
+  const bool wantg = a.grad != nullptr;
+  const T h2 = (T)(2.0 * a.h);
+  const T cq = (T)(0.25 * a.cw), ch = (T)(0.5 * a.cw);
+  for (int r = 0; r < a.nrhs; ++r) {
+    const int64_t base = (int64_t)r * a.g.state;
+    const T* __restrict__ u = (FIRST ? a.ybar : a.P) + base;
+    const T* __restrict__ lv = a.level + base;
+    T qa[2 * R + 1], qb[2 * R + 1], ql[2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+      const int64_t e = (int64_t)wrap(z0 - R + k, nz) * plane + pil;
+      qa[k] = (a.c2f ? a.c2f[e] : a.c2c) * u[e];
+      qb[k] = u[F3 + e];
+      ql[k] = wantg ? lv[F3 + e] : T(0);
+    }
+    for (int z = z0; z < zend; ++z) {
+      {
+        const int64_t e = (int64_t)wrap(z + R, nz) * plane + pil;
+        qa[2 * R] = (a.c2f ? a.c2f[e] : a.c2c) * u[e];
+        qb[2 * R] = u[F3 + e];
+        ql[2 * R] = wantg ? lv[F3 + e] : T(0);
+      }
+      const int64_t zoff = (int64_t)z * plane;
+      const int64_t row = zoff + (int64_t)y * nx;
+      const int64_t col = zoff + x;
+      const int64_t idx = zoff + pil;
+      T sb = T(0), sa = T(0);
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        sb += Fd<ORDER>::template w<T>(k) * (qb[R + 1 + k] - qb[R - 1 - k]);
+        sa += Fd<ORDER>::template w<T>(k) * (qa[R + 1 + k] - qa[R - 1 - k]);
+      }
+      T at[4];
+      at[0] = a.invx * dsum<T, ORDER>(u + F1 + row, x, nx, 1) +
+              a.invy * dsum<T, ORDER>(u + F2 + col, y, ny, nx);
+      at[1] = a.invx * dsum_c2<T, ORDER>(u + row, a.c2f ? a.c2f + row : nullptr, a.c2c, x, nx, 1);
+      at[2] = a.invy * dsum_c2<T, ORDER>(u + col, a.c2f ? a.c2f + col : nullptr, a.c2c, y, ny, nx);
+      at[0] += a.invz * sb;
+      at[3] = a.invz * sa;
+      T dv = T(0);
+      if (wantg) {
+        T sl = T(0);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+          sl += Fd<ORDER>::template w<T>(k) * (ql[R + 1 + k] - ql[R - 1 - k]);
+        T d = a.invx * dsum<T, ORDER>(lv + F1 + row, x, nx, 1) +
+              a.invy * dsum<T, ORDER>(lv + F2 + col, y, ny, nx);
+        d += a.invz * sl;
+        dv = -d;
+      }
+      if constexpr (FIRST) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t e = base + q * F1 + idx;
+          const T yb = a.ybar[e];
+          a.P[e] = ch * yb + h2 * (cq * at[q]);
+          a.Q[e] = ch * yb;
+        }
+        if (wantg)
+          a.grad[idx] += 2.0 * a.h * ((double)cq * (double)a.ybar[base + idx]) * (double)dv;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t e = base + q * F1 + idx;
+          const T qn = a.Q[e] + h2 * at[q];
+          if (!a.last) {
+            a.Q[e] = qn;
+          } else {
+            const double l1 = (double)qn;
+            const double v0 = l1 + (double)a.P[e];
+            const double f0 = a.h * l1;
+            if (a.first_seq) {
+              a.yacc[e] = v0;
+              a.facc[e] = f0;
+            } else {
+              a.yacc[e] += v0;
+              a.facc[e] += f0;
+            }
+          }
+        }
+        if (wantg) a.grad[idx] += 2.0 * a.h * (double)a.P[base + idx] * (double)dv;
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * R; ++k) {
+        qa[k] = qa[k + 1];
+        qb[k] = qb[k + 1];
+        ql[k] = ql[k + 1];
+      }
+    }
+  }
+}
+
 template <typename T>
 struct AdjFinalArgs {
   Geometry g;

@@ -207,6 +207,93 @@ __global__ __launch_bounds__(256) void lf_march2d(const StepArgs<T> a) {
   }
 }
 
+// 3-D acoustic leap-frog sweep, marching in z: a 256-thread block covers
+// 64 columns x 4 rows of one z-chunk of TZ planes; every thread walks up its
+// (x, y) column keeping the planes z-R..z+R of p and v_z in registers (the
+// z-derivatives), while the x- and y-derivatives read the current plane
+// (its rows are shared by the neighbouring blocks, which march in step).
+// Same arithmetic, in the same order, as lf_kernel.
+template <typename T, int ORDER, int TZ, bool NT>
+__global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
+  constexpr int R = Fd<ORDER>::R;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int ntx = (nx + 63) >> 6, nty = (ny + 3) >> 2;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx;
+  const int ty = (tile / ntx) % nty;
+  const int tz = tile / (ntx * nty);
+  const int x = tx * 64 + (threadIdx.x & 63);
+  const int y = ty * 4 + (threadIdx.x >> 6);
+  const int z0 = tz * TZ;
+  if (x >= nx || y >= ny || z0 >= nz) return;
+  const SeqDesc<T>& d = a.seq[blockIdx.y];
+  const int64_t rhs = blockIdx.z;
+  const int64_t base = rhs * a.g.state;
+  const int64_t F1 = a.g.field, F2 = 2 * a.g.field, F3 = 3 * a.g.field;
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t pil = (int64_t)y * nx + x;
+  const T* __restrict__ cp = d.cur + base;
+  const T* __restrict__ cvx = cp + F1;
+  const T* __restrict__ cvy = cp + F2;
+  const T* __restrict__ cvz = cp + F3;
+  T pw[2 * R + 1], vw[2 * R + 1];
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {
+    const int64_t e = (int64_t)wrap(z0 - R + k, nz) * plane + pil;
+    pw[k] = cp[e];
+    vw[k] = cvz[e];
+  }
+  const int zend = min(z0 + TZ, nz);
+  for (int z = z0; z < zend; ++z) {
+    {
+      const int64_t e = (int64_t)wrap(z + R, nz) * plane + pil;
+      pw[2 * R] = cp[e];
+      vw[2 * R] = cvz[e];
+    }
+    const int64_t zoff = (int64_t)z * plane;
+    const int64_t row = zoff + (int64_t)y * nx;
+    const int64_t col = zoff + x;
+    T szp = T(0), szv = T(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      szp += Fd<ORDER>::template w<T>(k) * (pw[R + 1 + k] - pw[R - 1 - k]);
+      szv += Fd<ORDER>::template w<T>(k) * (vw[R + 1 + k] - vw[R - 1 - k]);
+    }
+    const int64_t idx = zoff + pil;
+    const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
+    const T dvx = a.invx * dsum<T, ORDER>(cvx + row, x, nx, 1);
+    const T dvy = a.invy * dsum<T, ORDER>(cvy + col, y, ny, nx);
+    const T dvz = a.invz * szv;
+    T f[4];
+    f[0] = -(c2 * ((dvx + dvy) + dvz));
+    f[1] = -(a.invx * dsum<T, ORDER>(cp + row, x, nx, 1));
+    f[2] = -(a.invy * dsum<T, ORDER>(cp + col, y, ny, nx));
+    f[3] = -(a.invz * szp);
+    if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t e = base + q * F1 + idx;
+      const T o = d.old[e];
+      const T nw = o + d.h2 * f[q];
+      if (!(d.mode & MODE_LAST)) {
+        store<NT>(d.out + e, nw);
+      } else {
+        const T c = q == 0 ? pw[R] : (q == 3 ? vw[R] : (q == 1 ? cvx[idx] : cvy[idx]));
+        const double ys = 0.25 * (((double)o + 2.0 * (double)c) + (double)nw);
+        double v = d.cw * ys;
+        if (!(d.mode & MODE_FIRST)) v = a.acc[e] + v;
+        if (d.mode & MODE_FINAL) store<NT>(a.yout + e, (T)v);
+        else store<NT>(a.acc + e, v);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+      pw[k] = pw[k + 1];
+      vw[k] = vw[k + 1];
+    }
+  }
+}
+
 template <typename T, int ORDER, int OP>
 __global__ __launch_bounds__(256) void first_kernel(const FirstArgs<T> a) {
   constexpr int F = NFields<OP>::F;

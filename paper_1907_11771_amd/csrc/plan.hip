@@ -216,6 +216,7 @@ void fill_geometry(const gbs_plan* P, Geometry& g, T& c2c, const T*& c2f, T& ix,
 int resolve_variant(const gbs_plan* P) {
   if (P->variant != GBS_VARIANT_AUTO) return P->variant;
   if (P->prob.op == GBS_ACOUSTIC2D) return GBS_VARIANT_TEMPORAL;
+  if (P->prob.op == GBS_ACOUSTIC3D) return GBS_VARIANT_MARCH8;
   return GBS_VARIANT_FLAT;
 }
 
@@ -352,8 +353,11 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         hipEventRecord(ev->a, P->stream);
       }
       const unsigned blocks = WPG > 1 ? waves : (waves + 3) / 4;
-      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG>), dim3(blocks, n, P->prob.n_rhs),
-                         dim3(WPG > 1 ? 64 * WPG : 256), 0, P->stream, pa);
+      const dim3 grid(blocks, n, P->prob.n_rhs), blk(WPG > 1 ? 64 * WPG : 256);
+      if (P->prob.c2_field)
+        hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, true>), grid, blk, 0, P->stream, pa);
+      else
+        hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, false>), grid, blk, 0, P->stream, pa);
       if (ev) hipEventRecord(ev->b, P->stream);
     }
     EventPair* ev = nullptr;
@@ -378,8 +382,24 @@ void launch_march2d(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gz) {
                      P->stream, sa);
 }
 
+template <typename T, int ORDER, int TZ>
+void launch_march3d(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gz) {
+  const int ntx = (int)((P->prob.n[0] + 63) / 64);
+  const int nty = (int)((P->prob.n[1] + 3) / 4);
+  const int ntz = (int)((P->prob.n[2] + TZ - 1) / TZ);
+  hipLaunchKernelGGL((lf_march3d<T, ORDER, TZ, false>), dim3(ntx * nty * ntz, n, gz), dim3(256),
+                     0, P->stream, sa);
+}
+
 template <typename T, int ORDER, int OP>
 void launch_lf(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gx, unsigned gz) {
+  if constexpr (OP == OP_AC3D) {
+    switch (resolve_variant(P)) {
+      case GBS_VARIANT_MARCH8: launch_march3d<T, ORDER, 64>(P, sa, n, gz); return;
+      case GBS_VARIANT_MARCH16: launch_march3d<T, ORDER, 128>(P, sa, n, gz); return;
+      default: break;
+    }
+  }
   if constexpr (OP == OP_AC2D) {
     switch (resolve_variant(P)) {
       case GBS_VARIANT_MARCH8: launch_march2d<T, ORDER, 8, false>(P, sa, n, gz); return;
@@ -617,8 +637,11 @@ extern "C" int gbs_plan_set_variant(gbs_plan* P, int32_t variant) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
   if (variant < GBS_VARIANT_AUTO || variant > GBS_VARIANT_TEMPORAL_WG8)
     return fail(GBS_EINVAL, "unknown variant %d", variant);
-  if (variant >= GBS_VARIANT_MARCH8 && variant != GBS_VARIANT_PLAIN && P->prob.op != GBS_ACOUSTIC2D)
-    return fail(GBS_EUNSUPPORTED, "this variant is built for the 2-D acoustic operator only");
+  const bool march3d = P->prob.op == GBS_ACOUSTIC3D &&
+                       (variant == GBS_VARIANT_MARCH8 || variant == GBS_VARIANT_MARCH16);
+  if (variant >= GBS_VARIANT_MARCH8 && variant != GBS_VARIANT_PLAIN && !march3d &&
+      P->prob.op != GBS_ACOUSTIC2D)
+    return fail(GBS_EUNSUPPORTED, "this variant is not built for this operator");
   P->variant = variant;
   return GBS_OK;
 }
@@ -633,6 +656,56 @@ extern "C" int gbs_plan_set_band(gbs_plan* P, int32_t rows) {
 extern "C" int gbs_plan_get_variant(const gbs_plan* P, int32_t* variant) {
   if (!P || !variant) return fail(GBS_EINVAL, "null argument");
   *variant = resolve_variant(P);
+  return GBS_OK;
+}
+
+extern "C" int gbs_plan_autotune(gbs_plan* P, const void* y_in, void* y_out, int32_t macro_steps,
+                                 int32_t* variant_out, int32_t* band_out) {
+  if (!P || !y_in || !y_out || macro_steps < 1) return fail(GBS_EINVAL, "bad arguments");
+  if (P->prob.op != GBS_ACOUSTIC2D) {
+    // one kernel form for the other operators
+    if (variant_out) *variant_out = resolve_variant(P);
+    if (band_out) *band_out = P->band;
+    return GBS_OK;
+  }
+  const int variants[] = {GBS_VARIANT_TEMPORAL, GBS_VARIANT_TEMPORAL4, GBS_VARIANT_TEMPORAL_S5,
+                          GBS_VARIANT_TEMPORAL_WG4, GBS_VARIANT_TEMPORAL_WG8};
+  const int bands[] = {32, 64, 128};
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(GBS_EDEVICE, "creating events failed");
+  float best = 1e30f;
+  int bv = P->variant, bb = P->band;
+  int st = GBS_OK;
+  for (int v : variants) {
+    if (P->prob.fd_order == 8 && (v == GBS_VARIANT_TEMPORAL4 || v == GBS_VARIANT_TEMPORAL_S5))
+      continue;
+    for (int band : bands) {
+      P->variant = v;
+      P->band = band;
+      st = gbs_step(P, 0.0, 1, y_in, y_out);              // warm-up
+      if (st) break;
+      hipEventRecord(a, P->stream);
+      st = gbs_step(P, 0.0, macro_steps, y_in, y_out);
+      hipEventRecord(b, P->stream);
+      if (st) break;
+      if (hipEventSynchronize(b) != hipSuccess) {
+        st = fail(GBS_EDEVICE, "event sync failed");
+        break;
+      }
+      float ms = 0;
+      hipEventElapsedTime(&ms, a, b);
+      if (ms < best) { best = ms; bv = v; bb = band; }
+    }
+    if (st) break;
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  P->variant = bv;
+  P->band = bb;
+  if (st) return st;
+  if (variant_out) *variant_out = bv;
+  if (band_out) *band_out = bb;
   return GBS_OK;
 }
 
@@ -1220,6 +1293,11 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
   const unsigned gx = (unsigned)((P->field + 255) / 256);
   const unsigned gz = (unsigned)P->prob.n_rhs;
   hipStream_t s = P->stream;
+  // the 3-D operator's z-marching sweeps unless a flat form is chosen
+  const int v = resolve_variant(P);
+  const bool march = OP == OP_AC3D && (v == GBS_VARIANT_MARCH8 || v == GBS_VARIANT_MARCH16);
+  const unsigned mblocks = (unsigned)(((P->prob.n[0] + 63) / 64) * ((P->prob.n[1] + 3) / 4) *
+                                      ((P->prob.n[2] + 63) / 64));
 
   if (tbar && P->nrec)
     hipLaunchKernelGGL(inject_kernel<T>, dim3(1), dim3(64), 0, s, ybar, P->state, P->rec_dev,
@@ -1266,7 +1344,7 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
       d.cw = 0.0;
       d.amp = P->nsrc ? ricker(t0 + st * h, P->f0, P->delay) : 0.0;
       d.mode = 0;
-      hipLaunchKernelGGL((lf_kernel<T, ORDER, OP>), dim3(gx, 1, gz), dim3(256), 0, s, sa);
+      launch_lf<T, ORDER, OP>(P, sa, 1, gx, gz);
     }
     // transposed sequence
     aa.cw = P->w[j];
@@ -1276,14 +1354,20 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
     aa.P = bufA;
     aa.Q = bufB;
     aa.last = 0;
-    hipLaunchKernelGGL((adj_first_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
+    if (march)
+      hipLaunchKernelGGL((adj_march3d<T, ORDER, 64, true>), dim3(mblocks), dim3(256), 0, s, aa);
+    else
+      hipLaunchKernelGGL((adj_first_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
     for (int n = N - 1; n >= 1; --n) {
       const bool a_is_p = ((N - 1 - n) % 2) == 0;
       aa.P = a_is_p ? bufA : bufB;
       aa.Q = a_is_p ? bufB : bufA;
       aa.level = n == 0 ? y0 : L[n];
       aa.last = n == 1;
-      hipLaunchKernelGGL((adj_lf_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
+      if (march)
+        hipLaunchKernelGGL((adj_march3d<T, ORDER, 64, false>), dim3(mblocks), dim3(256), 0, s, aa);
+      else
+        hipLaunchKernelGGL((adj_lf_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
     }
   }
   AdjFinalArgs<T> fz;

@@ -161,7 +161,7 @@ __device__ __forceinline__ T lane_dsum_edges(T u, int lane, const T* left, const
   return s;
 }
 
-template <typename T, int ORDER, int G, bool SKEW1, int WPG>
+template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC>
 __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, const int band) {
   constexpr int R = Fd<ORDER>::R;
   constexpr int S = SKEW1 ? R + 1 : R;               // rows between consecutive levels
@@ -188,7 +188,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
   const int64_t F1 = w.field, F2 = 2 * w.field;
   const bool first = w.flags & PASS_FIRST;
   const bool final_ = w.flags & PASS_FINAL;
-  const bool varc = w.c2f != nullptr;
+  constexpr bool varc = VARC;                       // c^2 field (else the constant)
   const bool srcs = w.nsrc > 0;
   const T fac_lf = T(2) * w.h;
   const T* __restrict__ cur = w.cur + gx;
@@ -201,6 +201,19 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
     for (int s = 0; s < P; ++s)
 #pragma unroll
       for (int q = 0; q < 3; ++q) W[e][s][q] = T(0);
+
+  // c^2 queue in LDS, one per wavefront: the coefficient row is loaded once,
+  // with the input row, and level e reads it e S row steps later (a slot per
+  // lane, so no barrier).  Pre-filled with the rows above the first input row.
+  constexpr int CQ = G * S + 1;
+  constexpr int NWQ = WPG > 1 ? WPG : 4;
+  __shared__ T c2q[VARC ? NWQ : 1][VARC ? CQ : 1][64];
+  const int wq = WPG > 1 ? wave : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  T* const myq = &c2q[VARC ? wq : 0][0][lane];
+  if constexpr (VARC) {
+    for (int s = 1; s < CQ; ++s) myq[(CQ - s) * 64] = w.c2f[(int64_t)pmod(i0 - s, ny) * nx + gx];
+  }
+  int kq = 0;                                        // row step modulo CQ
 
   int irow = pmod(i0, ny);                           // wrapped row of A_0 at this row step
   for (int kb = 0; kb < niter; kb += P) {
@@ -217,6 +230,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
         nxt[0] = cur[e0];
         nxt[1] = cur[e0 + F1];
         nxt[2] = cur[e0 + F2];
+        if constexpr (VARC) myq[kq * 64] = w.c2f[e0 + gx];
         if (!first) {
           const int64_t e1 = (int64_t)wrap_sub(irow, S, ny) * nx;
           om[0] = old[e1];
@@ -268,9 +282,14 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
           sxv = lane_dsum<T, ORDER>(In[c][1]);
         }
         int row = 0;
-        if (varc || srcs || e == g) row = wrap_sub(irow, e * S, ny);
+        if (srcs || e == g) row = wrap_sub(irow, e * S, ny);
         const int64_t pt = (int64_t)row * nx + gx;
-        const T c2 = varc ? w.c2f[pt] : w.c2c;
+        T c2 = w.c2c;
+        if constexpr (VARC) {
+          int sl = kq - e * S;
+          if (sl < 0) sl += CQ;
+          c2 = myq[sl * 64];
+        }
         const T dvx = w.invx * sxv;
         const T dvy = w.invy * syv;
         T f[3];
@@ -326,6 +345,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
         for (int q = 0; q < 3; ++q) W[0][u][q] = nxt[q];
       }
       irow = irow + 1 == ny ? 0 : irow + 1;
+      kq = kq + 1 == CQ ? 0 : kq + 1;
       if constexpr (WPG > 1) __syncthreads();
     }
   }
@@ -335,8 +355,9 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
 // arguments), blockIdx.z the right-hand side; a workgroup of WPG wavefronts
 // covers one (strip, band), or with WPG = 1 each wavefront of a 4-wave block
 // does.
-template <typename T, int ORDER, int G, bool SKEW1, int WPG>
-__global__ __launch_bounds__(WPG > 1 ? 64 * WPG : 256) void pass2d(const PassArgs<T> a) {
+template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC>
+__global__ __launch_bounds__(WPG > 1 ? 64 * WPG : 256) __attribute__((amdgpu_waves_per_eu(2)))
+void pass2d(const PassArgs<T> a) {
   const PassSeq<T>& d = a.seq[blockIdx.y];
   const int unit = WPG > 1 ? (int)blockIdx.x
                            : __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -366,7 +387,7 @@ __global__ __launch_bounds__(WPG > 1 ? 64 * WPG : 256) void pass2d(const PassArg
   w.nsrc = a.g.nsrc;
 #pragma unroll
   for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = d.amp[e];
-  pass_body<T, ORDER, G, SKEW1, WPG>(w, strip, band);
+  pass_body<T, ORDER, G, SKEW1, WPG, VARC>(w, strip, band);
 }
 
 // A batch of problems: the passes of one round of every (instance, sequence)
@@ -429,7 +450,10 @@ void pass2d_batch(const BatchPassArgs<T> a) {
   w.nsrc = 0;
 #pragma unroll
   for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = 0.0;
-  pass_body<T, ORDER, G, SKEW1, WPG>(w, local % strips, local / strips);
+  if (w.c2f)
+    pass_body<T, ORDER, G, SKEW1, WPG, true>(w, local % strips, local / strips);
+  else
+    pass_body<T, ORDER, G, SKEW1, WPG, false>(w, local % strips, local / strips);
 }
 
 // y_out = sum_j c_j y*_j, j in ascending N, accumulated in FP64.

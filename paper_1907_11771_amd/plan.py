@@ -131,6 +131,17 @@ class GBSPlan:
     def set_variant(self, variant):
         B.check(B.lib().gbs_plan_set_variant(self.handle, int(variant)))
 
+    def autotune(self, y, out=None, macro_steps=5):
+        """Times the blocked variants and bands (gbs_plan_autotune) on a copy
+        of ``y`` and keeps the fastest; returns (variant, band)."""
+        self._check_state(y)
+        scratch = y.clone() if out is None else out
+        self._check_state(scratch)
+        v, b = ctypes.c_int32(), ctypes.c_int32()
+        B.check(B.lib().gbs_plan_autotune(self.handle, y.data_ptr(), scratch.data_ptr(),
+                                          int(macro_steps), ctypes.byref(v), ctypes.byref(b)))
+        return v.value, b.value
+
     def variant(self):
         out = ctypes.c_int32()
         B.check(B.lib().gbs_plan_get_variant(self.handle, ctypes.byref(out)))

@@ -88,3 +88,54 @@ def batch_sizes(count=64, choices=(256, 512, 768, 1024), seed=0):
     """Seeded uniform draw of per-instance square grid sizes."""
     rng = np.random.default_rng(seed)
     return [int(x) for x in rng.choice(np.array(choices), size=count)]
+
+
+def bandlimited_lognormal_speed(n, d=3, kmax=12, sigma=0.2, ell=0.1, seed=0):
+    """c = exp(sigma g) on an n^d grid, g a periodic Gaussian field made of
+    the integer wavevectors |k_i| <= kmax only: complex N(0,1) coefficients
+    (seeded, drawn on the (2 kmax + 1)^d cube independently of n) times the
+    square root of the spectral density exp(-ell^2 |2 pi k|^2 / 2), real part
+    of the inverse FFT, then centred and scaled to unit variance.  For
+    n > 2 kmax the grid resolves every product of two modes, so the mean and
+    variance, and hence the field values at coincident points, do not depend
+    on n: the field on a grid of n / m points per axis is the n-point field
+    sampled every m-th point (up to FFT rounding).  ell = 0.1 puts the
+    truncated spectrum below 1e-6 of its peak at kmax = 12."""
+    rng = np.random.default_rng(seed)
+    m = 2 * kmax + 1
+    coef = rng.standard_normal((m,) * d) + 1j * rng.standard_normal((m,) * d)
+    ks = np.arange(-kmax, kmax + 1)
+    k2 = np.zeros((m,) * d)
+    for ax in range(d):
+        sh = [1] * d
+        sh[ax] = m
+        k2 = k2 + (2 * np.pi * ks.reshape(sh)) ** 2
+    coef = coef * np.exp(-0.25 * ell ** 2 * k2)
+    if n <= 2 * kmax:
+        raise ValueError("the grid must resolve the field's modes (n > 2 kmax)")
+    full = np.zeros((n,) * d, dtype=np.complex128)
+    idx = np.ix_(*([ks % n] * d))
+    full[idx] = coef
+    g = np.real(np.fft.ifftn(full)) * float(n) ** d
+    g -= g.mean()
+    g /= g.std()
+    return np.exp(sigma * g)
+
+
+def ricker_source_3d(n, points, c_mean=1.0, cells_per_wavelength=10.0):
+    """Ricker point sources at the given grid points (z, y, x): peak
+    frequency f0 = c / (10 dx), delay 1.5 / f0, weight 1 / dx^3."""
+    dx = 1.0 / n
+    f0 = c_mean / (cells_per_wavelength * dx)
+    return dict(points=list(points), f0=f0, delay=1.5 / f0, weight=1.0 / dx ** 3)
+
+
+def plane_receivers_3d(n, count=128, z=None):
+    """``count`` receivers on the plane z = n/32 (default): a 16 x (count/16)
+    lattice of (y, x) points spread evenly.  Returns [(z, y, x)]."""
+    z = n // 32 if z is None else z
+    nyr = 16 if count >= 16 else count
+    nxr = count // nyr
+    ys = (n // nyr) * np.arange(nyr) + n // (2 * nyr)
+    xs = (n // nxr) * np.arange(nxr) + n // (2 * nxr)
+    return [(z, int(y), int(x)) for y in ys for x in xs]

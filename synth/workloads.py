@@ -51,3 +51,38 @@ def batch_instances(cfg=CONFIG_BATCH):
         H = stable_H(ISB_ORDER8_K6, float(c.max()), 1.0 / n, 2, SIGMA_FD4)
         out.append((n, c, H))
     return out
+
+
+# Differentiation: 2-D acoustic 1024^2, log-normal c^2 (seed 40), one Ricker
+# source at the centre, 128 receivers on the row n/32, 400 macro steps,
+# checkpoints every 20; data from c^2 * exp(0.1 g') (seed 41).
+CONFIG_ADJOINT = dict(name="adjoint_acoustic2d_1024_order8_k6", n=1024, r=2, n_macro=400,
+                      checkpoint_every=20, speed_seed=40, data_seed=41, receivers=128,
+                      scheme=schemes.ORDER8_K6)
+
+# 3-D acoustic 384^3, FD8, band-limited log-normal c (seed 50; the 96^3
+# parity grid samples the same field every 4th point), 8 right-hand sides
+# each with one Ricker point source at seeded positions on the 96-point
+# lattice, FP32 stepping with the FP64 combination, 100 macro steps; the
+# gradient: 128 receivers per right-hand side on the plane z = n/32, data from
+# c^2 exp(0.1 g') (g' seed 52), checkpoints every 20 macro steps.
+CONFIG_3D = dict(name="acoustic3d_384_fd8_order8_k6_rhs8", n=384, r=4, n_rhs=8, n_macro=100,
+                 speed_seed=50, source_seed=51, data_seed=52, kmax=12, receivers=128,
+                 checkpoint_every=20, scheme=schemes.ORDER8_K6)
+
+
+def sources_3d(n, count=8, seed=51, lattice=96):
+    """``count`` distinct seeded points (z, y, x) of the ``lattice``-point grid,
+    in [lattice/8, 7 lattice/8) per axis, scaled to an n-point grid (n a
+    multiple of ``lattice``)."""
+    import numpy as np
+    if n % lattice:
+        raise ValueError("n must be a multiple of the lattice size")
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < count:
+        p = tuple(int(v) for v in rng.integers(lattice // 8, lattice - lattice // 8, size=3))
+        if p not in pts:
+            pts.append(p)
+    m = n // lattice
+    return [(z * m, y * m, x * m) for z, y, x in pts]

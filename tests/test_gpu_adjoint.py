@@ -158,3 +158,28 @@ def test_full_size_gradient_vs_central_differences():
         fd = (float(loss_of(c2d, y0 + eps * dp)) - float(loss_of(c2d, y0 - eps * dp))) / (2 * eps)
         ad = float((gy * dp).sum())
         assert ad == pytest.approx(fd, rel=1e-7)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-14), (torch.float32, 1e-6)])
+def test_adjoint_3d_march_matches_flat(dtype, tol):
+    # the z-marching adjoint sweeps against the flat ones: same products and
+    # sums (the gradient adds the right-hand sides one at a time), ragged
+    # against the 64 x 4 x 64 tiles
+    shape = (70, 22, 90)
+    cs = fields.lognormal_speed(shape, seed=14)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / 90, 3, workloads.SIGMA_FD8)
+    rng = np.random.default_rng(15)
+    y0 = to_dev(rng.standard_normal((2, 4) + shape), dtype)
+    wbar = rng.standard_normal((2, 4) + shape)
+    res = []
+    for v in (B.VARIANT_FLAT, B.VARIANT_MARCH8):
+        plan = lib_plan(B.ACOUSTIC3D, (90, 22, 70), schemes.ORDER8_K6, H, fd_order=8, n_rhs=2,
+                        dtype=dtype, c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
+        plan.set_sources([0], [(30 * 22 + 5) * 90 + 7], [1e3], 25.0, 0.004)
+        plan.set_variant(v)
+        ybar = to_dev(wbar, dtype)
+        grad = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        plan.adjoint_step(0.003, y0, ybar, grad_c2=grad)
+        res.append((ybar.double().cpu().numpy(), grad.cpu().numpy()))
+    assert rel_err(res[1][0], res[0][0]) <= tol
+    assert rel_err(res[1][1], res[0][1]) <= tol

@@ -136,6 +136,25 @@ def test_kernel_variants_agree_bitwise(dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_3d_kernel_variants_agree_bitwise(dtype):
+    # z-marching (64 and 128 planes per thread), flat and per-sequence forms
+    shape = (70, 22, 90)                # z, y, x: ragged against 64 / 4 / 64
+    sch = schemes.ORDER8_K6
+    cs = fields.lognormal_speed(shape, seed=12)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / 90, 3, workloads.SIGMA_FD8)
+    y0 = to_dev(np.random.default_rng(13).standard_normal((2, 4) + shape), dtype)
+    outs = []
+    for v in (B.VARIANT_FLAT, B.VARIANT_MARCH8, B.VARIANT_MARCH16, B.VARIANT_PLAIN):
+        plan = lib_plan(B.ACOUSTIC3D, (90, 22, 70), sch, H, fd_order=8, n_rhs=2, dtype=dtype,
+                        c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
+        plan.set_sources([1], [(35 * 22 + 11) * 90 + 45], [1e3], 20.0, 0.01)
+        plan.set_variant(v)
+        outs.append(plan.step(y0, t0=0.005, n_macro=2))
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("variant,band", [(B.VARIANT_TEMPORAL, 128), (B.VARIANT_TEMPORAL, 7),
                                           (B.VARIANT_TEMPORAL4, 50), (B.VARIANT_TEMPORAL, 1000),
                                           (B.VARIANT_TEMPORAL_S5, 64), (B.VARIANT_TEMPORAL_S6, 33),
@@ -211,3 +230,23 @@ def test_acoustic2d_full_size_500_steps_vs_closed_form():
             float(np.max(np.abs(got[q] - want[q])) / np.max(np.abs(want[0]))) for q in range(3)]
     print("full-size rel errors", errs)
     assert max(errs) <= TOL64
+
+
+def test_plan_autotune_keeps_a_blocked_variant_with_the_same_result():
+    ny, nx = 160, 120
+    sch = schemes.ORDER8_K6
+    cs = fields.lognormal_speed((ny, nx), seed=5)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(nx, ny), 2,
+                           workloads.SIGMA_FD4)
+    y0 = to_dev(np.random.default_rng(6).standard_normal((1, 3, ny, nx)))
+    ref = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, c2_field=to_dev(cs ** 2), c_max=float(cs.max()))
+    ref.set_variant(B.VARIANT_FLAT)
+    want = ref.step(y0, n_macro=2).cpu().numpy()
+    plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, c2_field=to_dev(cs ** 2), c_max=float(cs.max()))
+    v, band = plan.autotune(y0, macro_steps=2)
+    assert v in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
+                 B.VARIANT_TEMPORAL_WG4, B.VARIANT_TEMPORAL_WG8)
+    assert band in (32, 64, 128)
+    assert plan.variant() == v
+    got = plan.step(y0, n_macro=2).cpu().numpy()
+    assert rel_err(got, want) <= 1e-13

@@ -188,3 +188,21 @@ def test_batch_plan_validation_on_host():
     st = B.lib().gbs_batch_plan_create(ctypes.byref(h), 3, probs, ctypes.byref(sc), Hs,
                                        FAKE_WS, 1 << 40, None)
     assert st == B.GBS_EUNSUPPORTED
+
+
+def test_3d_variants_on_host():
+    steps, w = _cfg2()
+    pr = B.make_problem(B.ACOUSTIC3D, (16, 12, 10), fd_order=8)
+    sc = B.make_scheme(8, steps, w)
+    nb = B.workspace_bytes(pr, sc)
+    h = B.plan_create(pr, sc, 1e-4, FAKE_WS, nb)
+    try:
+        v = ctypes.c_int32()
+        B.check(B.lib().gbs_plan_get_variant(h, ctypes.byref(v)))
+        assert v.value == B.VARIANT_MARCH8                      # z-marching by default
+        for ok in (B.VARIANT_FLAT, B.VARIANT_MARCH8, B.VARIANT_MARCH16, B.VARIANT_PLAIN):
+            B.check(B.lib().gbs_plan_set_variant(h, ok))
+        for bad in (B.VARIANT_MARCH8_NT, B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL_WG4):
+            assert B.lib().gbs_plan_set_variant(h, bad) == B.GBS_EUNSUPPORTED
+    finally:
+        B.plan_destroy(h)
