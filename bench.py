@@ -201,6 +201,8 @@ def bench_adjoint(args):
     plans = {k: make(dt, v) for k, (dt, v) in forms.items()}
     for k, (dt, _) in forms.items():
         warm(plans[k], dt)
+    for k, (dt, _) in forms.items():
+        run(plans[k], dt)          # full-length untimed pass: allocations settle
     f64, b64, g64, l64 = run(plans["f64"], torch.float64)
     f32, b32, g32, l32 = run(plans["f32"], torch.float32)
     fpl, bpl, gpl, _ = run(plans["plain"], torch.float64)

@@ -27,6 +27,7 @@
 #include "kernels.hpp"
 #include "temporal.hpp"
 #include "adjoint.hpp"
+#include "adjoint_blocked.hpp"
 
 namespace gbs {
 
@@ -259,12 +260,12 @@ struct PassSchedule {
 };
 
 int make_schedule(const int32_t* steps, int k, int G, int R, int wpg, PassSchedule& s,
-                  bool balance = false) {
+                  bool balance = false, int plus = 1) {
   double work[64] = {0};
   s.nrounds = 0;
   auto cost = [&](int g) { return g * (64.0 * wpg) / (64.0 * wpg - 2.0 * g * R); };
   for (int j = 0; j < k; ++j) {
-    const int E = steps[j] + 1;
+    const int E = steps[j] + plus;                   // evaluations of sequence j
     const int np = (E + G - 1) / G;
     if (np > 32) return fail(GBS_EUNSUPPORTED, "too many passes per sequence");
     s.npass[j] = np;
@@ -1273,10 +1274,244 @@ extern "C" int gbs_step_record(gbs_plan* P, double t0, int32_t n_macro, const vo
 
 namespace {
 
+// The temporally blocked adjoint serves the 2-D FD4 operator whenever the
+// plan's forward form is a blocked one.
+bool blocked_adjoint(const gbs_plan* P) {
+  return P->prob.op == GBS_ACOUSTIC2D && P->prob.fd_order == 4 && is_temporal(resolve_variant(P));
+}
+
 size_t adjoint_bytes(const gbs_plan* P) {
   const size_t elems = (size_t)P->prob.n_rhs * P->state;
   const size_t lb = align_up(elems * dsize(P->prob.dtype));
-  return (size_t)(P->nmax + 2) * lb + 2 * align_up(elems * 8);
+  const size_t lbd = align_up(elems * 8);
+  const size_t streaming = (size_t)(P->nmax + 2) * lb + 2 * lbd;
+  if (P->prob.op != GBS_ACOUSTIC2D || P->prob.fd_order != 4) return streaming;
+  // blocked: per sequence two pairs of Z levels (Y and Psi: two states
+  // each), lambda_0 + lambda_1 and h lambda_1 (FP64), a gradient field per
+  // right-hand side; then the sums over the sequences
+  const size_t gb = align_up((size_t)P->prob.n_rhs * P->field * 8);
+  const size_t blocked = (size_t)P->k * (8 * lb + 2 * lbd + gb) + 2 * lbd;
+  return std::max(streaming, blocked);
+}
+
+// G of the blocked adjoint passes (six fields per level in registers).
+template <typename T>
+constexpr int adj_pass_g() { return sizeof(T) == 8 ? 3 : 4; }
+
+// The forward levels (y_{N-1}, y_N) of every sequence from y_0: blocked
+// passes of the plan's forward form (G = 7) over N evaluations, the last
+// pass storing its last two levels.  pair_out[j] receives the pair.
+template <typename T, int G, bool SKEW1>
+int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX_SEQ][2]) {
+  constexpr int ORDER = 4, R = 2;
+  PassSchedule sch;
+  int st = make_schedule(P->steps, P->k, G, R, 1, sch, false, 0);
+  if (st) return st;
+  PassArgs<T> pa;
+  std::memset(&pa, 0, sizeof(pa));
+  T c2c, invz;
+  fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
+  pa.c2c = c2c;
+  pa.src_dev = P->src_dev;
+  pa.band = P->band;
+  pa.nbands = (int)((P->prob.n[1] + P->band - 1) / P->band);
+  const int nx = (int)P->prob.n[0];
+  for (int rr = 0; rr < sch.nrounds; ++rr) {
+    int n = 0, maxs = 0;
+    for (int r = 0; r < P->k; ++r) {
+      const int j = P->order[r];
+      const int q = rr - sch.round0[j];
+      if (q < 0 || q >= sch.npass[j]) continue;
+      PassSeq<T>& d = pa.seq[n++];
+      const double h = P->H / P->steps[j];
+      int s0 = 0;
+      for (int qq = 0; qq < q; ++qq) s0 += sch.gsz[j][qq];
+      d.g = sch.gsz[j][q];
+      d.h = (T)h;
+      d.flags = q == 0 ? PASS_FIRST : 0;
+      d.cur = q == 0 ? y0 : (const T*)P->pair[j][(q - 1) % 2][1];
+      d.old = q == 0 ? nullptr : (const T*)P->pair[j][(q - 1) % 2][0];
+      d.out_a = (T*)P->pair[j][q % 2][0];
+      d.out_b = (T*)P->pair[j][q % 2][1];
+      d.ystar = nullptr;
+      d.strips = (nx + (64 - 2 * d.g * R) - 1) / (64 - 2 * d.g * R);
+      for (int e = 0; e < d.g; ++e)
+        d.amp[e] = P->nsrc ? ricker(t0 + (s0 + e) * h, P->f0, P->delay) : 0.0;
+      maxs = std::max(maxs, d.strips);
+    }
+    pa.max_strips = maxs;
+    const unsigned blocks = ((unsigned)maxs * pa.nbands + 3) / 4;
+    const dim3 grid(blocks, n, P->prob.n_rhs), blk(256);
+    if (P->prob.c2_field)
+      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, 1, true>), grid, blk, 0, P->stream, pa);
+    else
+      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, 1, false>), grid, blk, 0, P->stream, pa);
+  }
+  for (int j = 0; j < P->k; ++j) {
+    const int q = sch.npass[j] - 1;
+    pair_out[j][0] = (const T*)P->pair[j][q % 2][0];   // y_{N-1}
+    pair_out[j][1] = (const T*)P->pair[j][q % 2][1];   // y_N
+  }
+  return GBS_OK;
+}
+
+// Sums over the sequences (ascending N) of the blocked adjoint's outputs.
+template <typename T>
+struct AdjSumArgs {
+  const double* ysum[GBS_MAX_SEQ];
+  const double* f1[GBS_MAX_SEQ];
+  const double* gsum[GBS_MAX_SEQ];
+  double* yacc;
+  double* facc;
+  double* grad;        // or null
+  int64_t n;           // elements of one whole state
+  int64_t field;
+  int32_t k, nrhs;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void adj_sum_kernel(const AdjSumArgs<T> a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  double ys = a.ysum[0][i], fs = a.f1[0][i];
+  for (int r = 1; r < a.k; ++r) {
+    ys += a.ysum[r][i];
+    fs += a.f1[r][i];
+  }
+  a.yacc[i] = ys;
+  a.facc[i] = fs;
+  if (a.grad && i < a.field) {
+    double gs = 0.0;
+    for (int r = 0; r < a.k; ++r)
+      for (int q = 0; q < a.nrhs; ++q) gs += a.gsum[r][(int64_t)q * a.field + i];
+    a.grad[i] += gs;
+  }
+}
+
+template <typename T>
+int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar,
+                        double* grad, char* ws) {
+  constexpr int ORDER = 4, R = 2;
+  constexpr int G = adj_pass_g<T>();
+  const size_t elems = (size_t)P->prob.n_rhs * P->state;
+  const size_t lb = align_up(elems * sizeof(T));
+  const size_t lbd = align_up(elems * 8);
+  const size_t gb = align_up((size_t)P->prob.n_rhs * P->field * 8);
+  hipStream_t s = P->stream;
+  // workspace: per sequence [Z pairs: 8 lb][ysum][f1][gsum], then yacc, facc
+  struct SeqBufs { T* z[2][2]; double* ysum; double* f1; double* gsum; } bufs[GBS_MAX_SEQ];
+  char* cur = ws;
+  for (int j = 0; j < P->k; ++j) {
+    for (int q = 0; q < 2; ++q)
+      for (int l = 0; l < 2; ++l) { bufs[j].z[q][l] = (T*)cur; cur += 2 * lb; }
+    bufs[j].ysum = (double*)cur; cur += lbd;
+    bufs[j].f1 = (double*)cur; cur += lbd;
+    bufs[j].gsum = (double*)cur; cur += gb;
+  }
+  double* yacc = (double*)cur; cur += lbd;
+  double* facc = (double*)cur;
+
+  if (tbar && P->nrec)
+    hipLaunchKernelGGL(inject_kernel<T>, dim3(1), dim3(64), 0, s, ybar, P->state, P->rec_dev,
+                       P->nrec, tbar);
+  // the forward pairs with the pass shape of the plan's forward form
+  // (its evaluations per pass and time skew; one wavefront per strip)
+  const T* pairs[GBS_MAX_SEQ][2];
+  int st;
+  switch (temporal_shape(resolve_variant(P), 4).G) {
+    case 4: st = forward_pairs<T, 4, false>(P, t0, y0, pairs); break;
+    case 5: st = forward_pairs<T, 5, true>(P, t0, y0, pairs); break;
+    case 6: st = forward_pairs<T, 6, true>(P, t0, y0, pairs); break;
+    default: st = forward_pairs<T, 7, false>(P, t0, y0, pairs); break;
+  }
+  if (st) return st;
+
+  PassSchedule sch;
+  st = make_schedule(P->steps, P->k, G, R, 1, sch, false, 0);
+  if (st) return st;
+  AdjPassArgs<T> pa;
+  std::memset(&pa, 0, sizeof(pa));
+  T c2c, invz;
+  fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
+  pa.c2c = c2c;
+  pa.src_dev = P->src_dev;
+  pa.zstride = (int64_t)elems;
+  pa.band = P->band;
+  pa.nbands = (int)((P->prob.n[1] + P->band - 1) / P->band);
+  const int nx = (int)P->prob.n[0];
+  for (int rr = 0; rr < sch.nrounds; ++rr) {
+    int n = 0, maxs = 0;
+    for (int r = 0; r < P->k; ++r) {
+      const int j = P->order[r];
+      const int q = rr - sch.round0[j];
+      if (q < 0 || q >= sch.npass[j]) continue;
+      AdjPassSeq<T>& d = pa.seq[n++];
+      const int N = P->steps[j];
+      const double h = P->H / N;
+      // the pass's input level is Z_{s0}: s0 = -1 for the first pass
+      int s0 = -1;
+      for (int qq = 0; qq < q; ++qq) s0 += sch.gsz[j][qq];
+      d.g = sch.gsz[j][q];
+      d.h = (T)h;
+      d.half_cw = (T)(0.5 * P->w[j]);
+      d.flags = (q == 0 ? ADJ_FIRST : 0) | (q == sch.npass[j] - 1 ? ADJ_FINAL : 0);
+      d.cur = q == 0 ? pairs[j][1] : bufs[j].z[(q - 1) % 2][1];
+      d.old = q == 0 ? pairs[j][0] : bufs[j].z[(q - 1) % 2][0];
+      d.ybar = ybar;
+      d.out_a = bufs[j].z[q % 2][0];
+      d.out_b = bufs[j].z[q % 2][1];
+      d.ysum = bufs[j].ysum;
+      d.f1 = bufs[j].f1;
+      d.gsum = bufs[j].gsum;
+      d.strips = (nx + (64 - 2 * d.g * R) - 1) / (64 - 2 * d.g * R);
+      // evaluation e+1 applies f to Y of level e, y_{N - s0 - e - 1}
+      for (int e = 0; e < d.g; ++e)
+        d.amp[e] = P->nsrc ? ricker(t0 + (N - s0 - e - 1) * h, P->f0, P->delay) : 0.0;
+      maxs = std::max(maxs, d.strips);
+    }
+    pa.max_strips = maxs;
+    const unsigned blocks = ((unsigned)maxs * pa.nbands + 3) / 4;
+    const dim3 grid(blocks, n, P->prob.n_rhs), blk(256);
+    if (P->prob.c2_field)
+      hipLaunchKernelGGL((adj_pass2d<T, G, true>), grid, blk, 0, s, pa);
+    else
+      hipLaunchKernelGGL((adj_pass2d<T, G, false>), grid, blk, 0, s, pa);
+  }
+  AdjSumArgs<T> sa;
+  std::memset(&sa, 0, sizeof(sa));
+  for (int r = 0; r < P->k; ++r) {
+    const int j = P->order[r];
+    sa.ysum[r] = bufs[j].ysum;
+    sa.f1[r] = bufs[j].f1;
+    sa.gsum[r] = bufs[j].gsum;
+  }
+  sa.yacc = yacc;
+  sa.facc = facc;
+  sa.grad = grad;
+  sa.n = (int64_t)elems;
+  sa.field = P->field;
+  sa.k = P->k;
+  sa.nrhs = P->prob.n_rhs;
+  hipLaunchKernelGGL((adj_sum_kernel<T>), dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s,
+                     sa);
+  AdjFinalArgs<T> fz;
+  std::memset(&fz, 0, sizeof(fz));
+  T ix, iy, iz;
+  fill_geometry<T>(P, fz.g, fz.c2c, fz.c2f, ix, iy, iz);
+  fz.invx = (double)P->prob.n[0] / 12.0;
+  fz.invy = (double)P->prob.n[1] / 12.0;
+  fz.invz = (double)P->prob.n[2] / 12.0;
+  fz.yacc = yacc;
+  fz.facc = facc;
+  fz.y0 = y0;
+  fz.ybar = ybar;
+  fz.grad = grad;
+  fz.nrhs = P->prob.n_rhs;
+  const unsigned gx = (unsigned)((P->field + 255) / 256);
+  hipLaunchKernelGGL((adj_final_kernel<T, ORDER, OP_AC2D>), dim3(gx), dim3(256), 0, s, fz);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GBS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return GBS_OK;
 }
 
 template <typename T, int ORDER, int OP>
@@ -1396,6 +1631,7 @@ int adjoint_dispatch(gbs_plan* P, double t0, const void* y0, void* ybar, const v
   const T* a = (const T*)y0;
   T* b = (T*)ybar;
   const T* c = (const T*)tbar;
+  if (blocked_adjoint(P)) return adjoint_blocked_run<T>(P, t0, a, b, c, grad, ws);
   if (P->prob.fd_order == 4) {
     if (P->prob.op == GBS_ACOUSTIC2D) return adjoint_run<T, 4, OP_AC2D>(P, t0, a, b, c, grad, ws);
     return adjoint_run<T, 4, OP_AC3D>(P, t0, a, b, c, grad, ws);

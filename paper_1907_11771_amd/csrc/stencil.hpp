@@ -74,6 +74,31 @@ struct SrcDesc {
   int32_t pad;
 };
 
+// The point sources of right-hand side `rhs` in one lane's column, found
+// once per wavefront: the blocked passes evaluate source terms only in
+// wavefronts where some lane owns a source column (`any`, wave-uniform), and
+// a lane with exactly one source compares rows against a register copy.
+struct LaneSource {
+  double w = 0.0;
+  int row = -1;
+  int count = 0;     // sources in this lane's column
+  bool any = false;
+};
+
+__device__ __forceinline__ LaneSource lane_source(const SrcDesc* src, int nsrc, int64_t rhs, int gx,
+                                                  int nx) {
+  LaneSource ls;
+  for (int k = 0; k < nsrc; ++k) {
+    if (src[k].rhs == rhs && (int)(src[k].idx % nx) == gx) {
+      ++ls.count;
+      ls.row = (int)(src[k].idx / nx);
+      ls.w = src[k].w;
+    }
+  }
+  ls.any = __ballot(ls.count > 0) != 0;
+  return ls;
+}
+
 struct Geometry {
   int32_t nx, ny, nz;
   int32_t nsrc;

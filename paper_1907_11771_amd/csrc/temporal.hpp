@@ -189,7 +189,8 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
   const bool first = w.flags & PASS_FIRST;
   const bool final_ = w.flags & PASS_FINAL;
   constexpr bool varc = VARC;                       // c^2 field (else the constant)
-  const bool srcs = w.nsrc > 0;
+  const LaneSource ls = w.nsrc > 0 ? lane_source(w.src, w.nsrc, w.rhs, gx, nx) : LaneSource();
+  const bool srcs = ls.any;
   const T fac_lf = T(2) * w.h;
   const T* __restrict__ cur = w.cur + gx;
   const T* __restrict__ old = first ? cur : w.old + gx;
@@ -296,7 +297,13 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
         f[0] = -(c2 * (dvx + dvy));
         f[1] = -(w.invx * sxp);
         f[2] = -(w.invy * syp);
-        if (srcs) f[0] += source_term<T>(w.src, w.nsrc, w.rhs, pt, w.amp[e - 1]);
+        if (srcs) {
+          if (ls.count == 1) {
+            if (row == ls.row) f[0] += (T)(ls.w * w.amp[e - 1]);
+          } else if (ls.count > 1) {
+            f[0] += source_term<T>(w.src, w.nsrc, w.rhs, pt, w.amp[e - 1]);
+          }
+        }
         T nw[3];
         if (e == 1) {
           if (first) {

@@ -183,3 +183,32 @@ def test_adjoint_3d_march_matches_flat(dtype, tol):
         res.append((ybar.double().cpu().numpy(), grad.cpu().numpy()))
     assert rel_err(res[1][0], res[0][0]) <= tol
     assert rel_err(res[1][1], res[0][1]) <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+@pytest.mark.parametrize("band", [64, 19])
+def test_blocked_adjoint_matches_streaming(dtype, tol, band):
+    # the temporally blocked adjoint (levels regenerated backwards, Psi
+    # variables) against the streaming one (levels stored), two right-hand
+    # sides with a source, ragged against strips and bands
+    ny, nx = 150, 130
+    cs = fields.lognormal_speed((ny, nx), seed=16)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(nx, ny), 2,
+                           workloads.SIGMA_FD4)
+    rng = np.random.default_rng(17)
+    y0 = to_dev(rng.standard_normal((2, 3, ny, nx)), dtype)
+    wbar = rng.standard_normal((2, 3, ny, nx))
+    s = fields.ricker_source_2d(max(nx, ny), cells_per_wavelength=6.0)
+    res = []
+    for v in (B.VARIANT_FLAT, B.VARIANT_TEMPORAL):
+        plan = lib_plan(B.ACOUSTIC2D, (nx, ny), schemes.ORDER8_K6, H, n_rhs=2, dtype=dtype,
+                        c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
+        plan.set_sources([1], [70 * nx + 40], [s["weight"] * 1e-3], s["f0"], s["delay"])
+        plan.set_variant(v)
+        B.check(B.lib().gbs_plan_set_band(plan.handle, band))
+        ybar = to_dev(wbar, dtype)
+        grad = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+        plan.adjoint_step(0.9 * s["delay"], y0, ybar, grad_c2=grad)
+        res.append((ybar.double().cpu().numpy(), grad.cpu().numpy()))
+    assert rel_err(res[1][0], res[0][0]) <= tol
+    assert rel_err(res[1][1], res[0][1]) <= tol
