@@ -72,6 +72,8 @@ def bench_batch(args):
     from synth import workloads
 
     cfg = workloads.CONFIG_BATCH
+    if args.steps == 500:                 # the default: the batch workload's own length
+        args.steps = cfg["n_macro"]
     steps, w, _ = scheme_weights(cfg["scheme"])
     dev = torch.device("cuda:0")
     dtype = torch.float64 if args.dtype == "f64" else torch.float32

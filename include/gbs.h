@@ -139,7 +139,11 @@ int gbs_plan_workspace_bytes(const gbs_problem* prob, const gbs_scheme* sch, siz
  *              H * rho must not exceed the ISB of the scheme, with rho =
  *              c_max * sigma * sqrt(sum_axes n_a^2), sigma = max_theta of the
  *              stencil's symbol (App. A: the operator's eigenvalues must lie
- *              in the stability domain) -> GBS_EUNSTABLE.
+ *              in the stability domain) -> GBS_EUNSTABLE.  The ISB is that of
+ *              the exact order-p scheme the FP64 weights round (the weights
+ *              beyond the first p/2 as given, the first p/2 re-solved from
+ *              the order constraints), when that moves no weight by more
+ *              than 1e-12 of sum |c|; otherwise that of the given weights.
  *   workspace  device, at least gbs_plan_workspace_bytes(); owned by the
  *              caller, must outlive the plan, and must not be shared by
  *              plans whose calls overlap.
@@ -276,17 +280,26 @@ int gbs_plan_destroy(gbs_plan* plan);
  * gbs_step_record — as gbs_step, and after every macro step m writes
  *   traces[m][r] = p[rhs_r][flat_index_r] of the new state (device array
  *   [n_macro][n_rec] in the plan's dtype).
- * gbs_plan_adjoint_workspace_bytes — scratch for gbs_adjoint_step: the
- *   forward levels of one sequence (N_max of them), two adjoint levels and
- *   two FP64 accumulator states.
- * gbs_adjoint_step — one macro step backwards.  y_in: forward state at t0
- *   (start of the macro step); ybar (device, in/out): on entry the adjoint
- *   of the state at t0 + H, on return the adjoint of the state at t0;
- *   trace_bar (device [n_rec], nullable): adjoint of the traces recorded at
- *   t0 + H, added to ybar's pressure at the receivers first; grad_c2
- *   (device FP64 [Z][Y][X], nullable, needs a c^2 field): dL/dc^2 of this
- *   macro step is added to it.  The forward levels are recomputed from y_in
- *   (with the plan's sources) in the adjoint workspace.
+ * gbs_plan_adjoint_workspace_bytes — scratch for gbs_adjoint_step, the
+ *   larger of the two forms' needs: streaming, the forward levels of one
+ *   sequence (N_max of them), two adjoint levels and two FP64 accumulator
+ *   states; temporally blocked (2-D, FD4), per sequence two pairs of
+ *   (forward level, adjoint level) states, two FP64 states and one FP64
+ *   gradient field per right-hand side, plus two FP64 states.
+ * gbs_adjoint_step — one macro step backwards (the transpose of the
+ *   discrete step; the paper defines the forward step only, Sect. 2.1 and
+ *   3.2).  y_in: forward state at t0 (start of the macro step); ybar
+ *   (device, in/out): on entry the adjoint of the state at t0 + H, on return
+ *   the adjoint of the state at t0; trace_bar (device [n_rec], nullable):
+ *   adjoint of the traces recorded at t0 + H, added to ybar's pressure at
+ *   the receivers first; grad_c2 (device FP64 [Z][Y][X], nullable, needs a
+ *   c^2 field): dL/dc^2 of this macro step is added to it.  The forward
+ *   levels are recomputed from y_in (with the plan's sources): the 2-D FD4
+ *   operator with a temporally blocked variant (the default) regenerates
+ *   them by running the leap-frog backwards from the last two levels, which
+ *   blocked forward passes leave in the plan's workspace (so calls on one
+ *   plan must not overlap, as for gbs_step); every other case stores the
+ *   levels of one sequence at a time in the adjoint workspace.
  */
 int gbs_plan_set_receivers(gbs_plan* plan, int32_t n_rec, const int32_t* rhs,
                            const int64_t* flat_index);

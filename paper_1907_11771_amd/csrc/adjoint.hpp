@@ -375,12 +375,18 @@ __global__ void gather_kernel(const T* __restrict__ y, int64_t state, const RecD
   out[r] = y[(int64_t)rec[r].rhs * state + rec[r].idx];
 }
 
-// One thread per receiver, in receiver order, so that receivers sharing a
-// grid point add up deterministically.
+// One thread walks the receivers in order, so that receivers sharing a grid
+// point add up deterministically; with distinct points (checked on the host)
+// every receiver has its own thread.
 template <typename T>
 __global__ void inject_kernel(T* __restrict__ ybar, int64_t state, const RecDesc* rec, int n,
-                              const T* __restrict__ tbar) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+                              const T* __restrict__ tbar, int distinct) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (distinct) {
+    if (t < n) ybar[(int64_t)rec[t].rhs * state + rec[t].idx] += tbar[t];
+    return;
+  }
+  if (t != 0) return;
   for (int r = 0; r < n; ++r) ybar[(int64_t)rec[r].rhs * state + rec[r].idx] += tbar[r];
 }
 

@@ -70,6 +70,7 @@ struct gbs_plan {
   SrcDesc* src_dev = nullptr;
   // receivers (device table in the workspace)
   int nrec = 0;
+  bool rec_distinct = true;   // no two receivers share a (rhs, point)
   RecDesc* rec_dev = nullptr;
   double f0 = 0, delay = 0;
   // leap-frog kernel variant (GBS_VARIANT_*) and rows per band of the
@@ -167,9 +168,37 @@ size_t workspace_bytes(const gbs_problem* p, int k) {
 // rho = c_max sigma sqrt(sum_a n_a^2)) must lie in the stability domain.
 int check_stable(const gbs_problem* prob, const gbs_scheme* sch, double H) {
   if (prob->flags & GBS_FLAG_NO_STABILITY_CHECK) return GBS_OK;
-  std::vector<Rational> c(sch->k);
-  for (int j = 0; j < sch->k; ++j) c[j] = Rational::from_double(sch->weights[j]);
-  const double isb = isb_of(sch->k, sch->steps, c);
+  // The FP64 weights stand for an exact scheme: the free weights (those
+  // beyond the first p/2 in the given order) as given, the dependent ones
+  // re-solved exactly from the order constraints (Sect. 3.7).  Taken at their
+  // binary values instead, rounding can leave sum_j c_j = 1 + 1 ulp, which
+  // puts the origin itself outside the stability domain (ISB 0).  The
+  // projection is used only if it moves no weight by more than 1e-12 of
+  // sum |c| (otherwise the given weights are not an order-p scheme and are
+  // checked as they are).
+  const int k = sch->k, rows = sch->p / 2;
+  std::vector<Rational> c(k);
+  for (int j = 0; j < k; ++j) c[j] = Rational::from_double(sch->weights[j]);
+  if (k >= rows && rows > 0) {
+    std::vector<int32_t> fidx;
+    std::vector<Rational> cf;
+    for (int j = rows; j < k; ++j) {
+      fidx.push_back(j);
+      cf.push_back(c[j]);
+    }
+    std::vector<Rational> cp;
+    const std::string saved = g_last_error;
+    if (exact_weights(sch->p, k, sch->steps, k - rows, fidx.data(), cf.data(), cp) == GBS_OK) {
+      double sum = 0, dev = 0;
+      for (int j = 0; j < k; ++j) {
+        sum += std::fabs(sch->weights[j]);
+        dev = std::max(dev, std::fabs(cp[j].to_double() - sch->weights[j]));
+      }
+      if (dev <= 1e-12 * sum) c = cp;
+    }
+    g_last_error = saved;                            // a failed projection is no error
+  }
+  const double isb = isb_of(k, sch->steps, c);
   const int d = dims_of(prob->op);
   double s2 = 0;
   for (int a = 0; a < d; ++a) s2 += (double)prob->n[a] * (double)prob->n[a];
@@ -1244,6 +1273,10 @@ extern "C" int gbs_plan_set_receivers(gbs_plan* P, int32_t n_rec, const int32_t*
                                hipMemcpyHostToDevice, P->stream) != hipSuccess ||
                 hipStreamSynchronize(P->stream) != hipSuccess))
     return fail(GBS_EDEVICE, "copying the receivers to the workspace failed");
+  std::vector<std::pair<int32_t, int64_t>> keys(n_rec);
+  for (int i = 0; i < n_rec; ++i) keys[i] = {rhs[i], flat_index[i]};
+  std::sort(keys.begin(), keys.end());
+  P->rec_distinct = std::adjacent_find(keys.begin(), keys.end()) == keys.end();
   P->nrec = n_rec;
   return GBS_OK;
 }
@@ -1412,8 +1445,8 @@ int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* t
   double* facc = (double*)cur;
 
   if (tbar && P->nrec)
-    hipLaunchKernelGGL(inject_kernel<T>, dim3(1), dim3(64), 0, s, ybar, P->state, P->rec_dev,
-                       P->nrec, tbar);
+    hipLaunchKernelGGL(inject_kernel<T>, dim3((unsigned)((P->nrec + 255) / 256)), dim3(256), 0, s,
+                       ybar, P->state, P->rec_dev, P->nrec, tbar, (int)P->rec_distinct);
   // the forward pairs with the pass shape of the plan's forward form
   // (its evaluations per pass and time skew; one wavefront per strip)
   const T* pairs[GBS_MAX_SEQ][2];
@@ -1535,8 +1568,8 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
                                       ((P->prob.n[2] + 63) / 64));
 
   if (tbar && P->nrec)
-    hipLaunchKernelGGL(inject_kernel<T>, dim3(1), dim3(64), 0, s, ybar, P->state, P->rec_dev,
-                       P->nrec, tbar);
+    hipLaunchKernelGGL(inject_kernel<T>, dim3((unsigned)((P->nrec + 255) / 256)), dim3(256), 0, s,
+                       ybar, P->state, P->rec_dev, P->nrec, tbar, (int)P->rec_distinct);
 
   FirstArgs<T> fa;
   StepArgs<T> sa;

@@ -87,11 +87,15 @@ def test_dot_product_identity_with_library_forward(dtype, tol):
     assert abs(lhs - rhs) <= tol * max(abs(lhs), 1.0)
 
 
-def test_checkpointed_misfit_gradient_matches_oracle():
+@pytest.mark.parametrize("duplicate", [False, True])
+def test_checkpointed_misfit_gradient_matches_oracle(duplicate):
     plan, op, H = _setup2d(nx=32, ny=24)
     steps, c = oracle_weights(schemes.ORDER8_K6)
     nx, ny = 32, 24
     rec = fields.edge_receivers_2d(nx, count=8, row=3)
+    if duplicate:
+        # two receivers at one point: their adjoints are injected in order
+        rec = np.concatenate([rec, rec[2:3]])
     plan.set_receivers([0] * len(rec), [int(r[0]) * nx + int(r[1]) for r in rec])
     n_macro = 7
     y0 = fields.acoustic2d_pulse_modes(nx, n_modes=4, kmax=3, width=0.1, seed=7)[:, :ny, :]

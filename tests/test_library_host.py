@@ -206,3 +206,22 @@ def test_3d_variants_on_host():
             assert B.lib().gbs_plan_set_variant(h, bad) == B.GBS_EUNSUPPORTED
     finally:
         B.plan_destroy(h)
+
+
+def test_stability_check_uses_the_exact_scheme_behind_rounded_weights():
+    # the fully determined order-8 scheme {2,16,18,20}: its FP64 weights sum
+    # to more than 1 by rounding (taken literally, ISB 0); the plan checks
+    # the exact scheme (ISB 12.177) and still rejects H beyond it
+    steps = [2, 16, 18, 20]
+    w, isb = B.weights(8, steps)
+    assert isb == pytest.approx(12.177232, abs=1e-5)
+    assert B.isb(steps, w) < 1.0
+    pr = B.make_problem(B.ACOUSTIC2D, (64, 64))
+    sc = B.make_scheme(8, steps, w)
+    nb = B.workspace_bytes(pr, sc)
+    rho = 1.3722220 * (64 ** 2 * 2) ** 0.5
+    h = B.plan_create(pr, sc, 0.99 * isb / rho, FAKE_WS, nb)
+    B.plan_destroy(h)
+    with pytest.raises(B.GBSError) as ei:
+        B.plan_create(pr, sc, 1.01 * isb / rho, FAKE_WS, nb)
+    assert ei.value.status == B.GBS_EUNSTABLE
