@@ -368,7 +368,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=0,
-                    help="stepping-kernel variant (0 = the library's choice)")
+                    help="stepping-kernel variant (0: autotuned by the library)")
     ap.add_argument("--band", type=int, default=0,
                     help="rows per band of the temporally blocked passes (0 = default)")
     ap.add_argument("--workload", default="acoustic2d",
@@ -417,12 +417,18 @@ def main():
     dev = torch.device("cuda:0")
     plan = GBSPlan(B.ACOUSTIC2D, (n, n), cfg["scheme"]["p"], steps, w, cfg["H"], fd_order=4,
                    dtype=torch.float64, c2=cfg["c2"], device=dev)
-    if args.variant:
-        plan.set_variant(args.variant)
-    if args.band:
-        B.check(B.lib().gbs_plan_set_band(plan.handle, args.band))
     y = torch.from_numpy(y0[None]).to(dev)
     out = torch.empty_like(y)
+    tuned = None
+    if args.variant or args.band:
+        if args.variant:
+            plan.set_variant(args.variant)
+        if args.band:
+            B.check(B.lib().gbs_plan_set_band(plan.handle, args.band))
+    else:
+        # the library's own autotuner picks the blocked variant and band
+        # (untimed; it writes only into `out`)
+        tuned = plan.autotune(y, out, macro_steps=5)
 
     plan.step(y, out, n_macro=args.warmup)
     torch.cuda.synchronize()
@@ -462,7 +468,8 @@ def main():
         dtype="f64", data="synthetic",
         config=dict(workload=cfg["name"], grid=[n, n], fields=3, fd_order=4,
                     scheme_order=8, sequences=steps, evals_per_macro_step=1 + sum(steps),
-                    H=cfg["H"], macro_steps_timed=args.steps, kernel_variant=variant),
+                    H=cfg["H"], macro_steps_timed=args.steps, kernel_variant=variant,
+                    autotuned=dict(variant=tuned[0], band=tuned[1]) if tuned else None),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                       traffic_bytes_per_launch=measured, kernel=kstep,

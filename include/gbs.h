@@ -177,7 +177,9 @@ int gbs_step(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void*
 /*
  * gbs_plan_set_variant — choose the leap-frog kernel (all variants compute
  * the same values in the same order; they differ in work layout only):
- *   GBS_VARIANT_AUTO        library's choice (default)
+ *   GBS_VARIANT_AUTO        library's choice (default): 2-D acoustic
+ *                           GBS_VARIANT_TEMPORAL_S5, 3-D acoustic
+ *                           GBS_VARIANT_MARCH8, 1-D GBS_VARIANT_FLAT
  *   GBS_VARIANT_FLAT        one grid point per thread (every operator)
  *   GBS_VARIANT_MARCH8/16   2-D acoustic: each thread marches 8 / 16 rows,
  *                           y-stencil rows kept in registers; 3-D acoustic:
@@ -226,8 +228,8 @@ int gbs_plan_get_variant(const gbs_plan* plan, int32_t* variant);
 
 /*
  * gbs_plan_autotune — the project's own tuner: times every temporally
- * blocked variant (those built for the plan's stencil order) at 32, 64 and
- * 128 rows per band, macro_steps macro steps each from y_in into y_out
+ * blocked variant (those built for the plan's stencil order) at 32, 64, 96
+ * and 128 rows per band, macro_steps macro steps each from y_in into y_out
  * (device buffers of one state, may be the same; y_out is overwritten), on
  * the plan's stream, and keeps the fastest.  Operators other than the 2-D
  * acoustic one have a single form: the call returns it unchanged.

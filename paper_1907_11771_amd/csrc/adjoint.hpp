@@ -173,6 +173,23 @@ __global__ __launch_bounds__(256) void adj_lf_kernel(const AdjArgs<T> a) {
   if (a.grad) a.grad[idx] += gsum;
 }
 
+// dsum_c2 with 32-bit element indices from uniform base pointers (see
+// dsum32).
+template <typename T, int ORDER>
+__device__ __forceinline__ T dsum_c2_32(const T* __restrict__ u, const T* __restrict__ c2f, T c2c,
+                                        uint32_t c, int i, int n, uint32_t s) {
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < Fd<ORDER>::R; ++k) {
+    const uint32_t iu = c + (uint32_t)(wrap(i + k + 1, n) - i) * s;
+    const uint32_t id = c + (uint32_t)(wrap(i - k - 1, n) - i) * s;
+    const T up = (c2f ? c2f[iu] : c2c) * u[iu];
+    const T dn = (c2f ? c2f[id] : c2c) * u[id];
+    acc += Fd<ORDER>::template w<T>(k) * (up - dn);
+  }
+  return acc;
+}
+
 // The two sweeps above for the 3-D operator, marching in z (the layout of
 // lf_march3d): each thread walks up its (x, y) column keeping the planes
 // z-R..z+R of c^2 u_p, u_vz and the level's v_z in registers, while the x-
@@ -180,9 +197,11 @@ __global__ __launch_bounds__(256) void adj_lf_kernel(const AdjArgs<T> a) {
 // else u = P.  The right-hand sides are looped over inside the thread, so
 // the c^2 gradient of a point has one writer.  Same products and sums, in
 // the same order, as adj_first_kernel / adj_lf_kernel (the gradient adds
-// the right-hand sides' terms one at a time).
+// the right-hand sides' terms one at a time).  Fields of fewer than 2^31
+// points (32-bit element indices).
 template <typename T, int ORDER, int TZ, bool FIRST>
-__global__ __launch_bounds__(256) void adj_march3d(const AdjArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
+void adj_march3d(const AdjArgs<T> a) {
   constexpr int R = Fd<ORDER>::R;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int ntx = (nx + 63) >> 6, nty = (ny + 3) >> 2;
@@ -194,36 +213,40 @@ __global__ __launch_bounds__(256) void adj_march3d(const AdjArgs<T> a) {
   const int y = ty * 4 + (threadIdx.x >> 6);
   const int z0 = tz * TZ;
   if (x >= nx || y >= ny || z0 >= nz) return;
-  const int64_t F1 = a.g.field, F2 = 2 * a.g.field, F3 = 3 * a.g.field;
-  const int64_t plane = (int64_t)nx * ny;
-  const int64_t pil = (int64_t)y * nx + x;
+  const int64_t F1 = a.g.field;
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  const uint32_t pil = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
+  const uint32_t snx = (uint32_t)nx;
   const int zend = min(z0 + TZ, nz);
   const bool wantg = a.grad != nullptr;
   const T h2 = (T)(2.0 * a.h);
   const T cq = (T)(0.25 * a.cw), ch = (T)(0.5 * a.cw);
+  const T* __restrict__ c2f = a.c2f;
   for (int r = 0; r < a.nrhs; ++r) {
     const int64_t base = (int64_t)r * a.g.state;
-    const T* __restrict__ u = (FIRST ? a.ybar : a.P) + base;
-    const T* __restrict__ lv = a.level + base;
+    const T* __restrict__ up = (FIRST ? a.ybar : a.P) + base;     // u_p
+    const T* __restrict__ ux = up + F1;
+    const T* __restrict__ uy = up + 2 * F1;
+    const T* __restrict__ uz = up + 3 * F1;
+    const T* __restrict__ lx = a.level + base + F1;
+    const T* __restrict__ ly = lx + F1;
+    const T* __restrict__ lz = ly + F1;
     T qa[2 * R + 1], qb[2 * R + 1], ql[2 * R + 1];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) {
-      const int64_t e = (int64_t)wrap(z0 - R + k, nz) * plane + pil;
-      qa[k] = (a.c2f ? a.c2f[e] : a.c2c) * u[e];
-      qb[k] = u[F3 + e];
-      ql[k] = wantg ? lv[F3 + e] : T(0);
+      const uint32_t e = (uint32_t)wrap(z0 - R + k, nz) * plane + pil;
+      qa[k] = (c2f ? c2f[e] : a.c2c) * up[e];
+      qb[k] = uz[e];
+      ql[k] = wantg ? lz[e] : T(0);
     }
     for (int z = z0; z < zend; ++z) {
       {
-        const int64_t e = (int64_t)wrap(z + R, nz) * plane + pil;
-        qa[2 * R] = (a.c2f ? a.c2f[e] : a.c2c) * u[e];
-        qb[2 * R] = u[F3 + e];
-        ql[2 * R] = wantg ? lv[F3 + e] : T(0);
+        const uint32_t e = (uint32_t)wrap(z + R, nz) * plane + pil;
+        qa[2 * R] = (c2f ? c2f[e] : a.c2c) * up[e];
+        qb[2 * R] = uz[e];
+        ql[2 * R] = wantg ? lz[e] : T(0);
       }
-      const int64_t zoff = (int64_t)z * plane;
-      const int64_t row = zoff + (int64_t)y * nx;
-      const int64_t col = zoff + x;
-      const int64_t idx = zoff + pil;
+      const uint32_t idx = (uint32_t)z * plane + pil;
       T sb = T(0), sa = T(0);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
@@ -231,10 +254,10 @@ __global__ __launch_bounds__(256) void adj_march3d(const AdjArgs<T> a) {
         sa += Fd<ORDER>::template w<T>(k) * (qa[R + 1 + k] - qa[R - 1 - k]);
       }
       T at[4];
-      at[0] = a.invx * dsum<T, ORDER>(u + F1 + row, x, nx, 1) +
-              a.invy * dsum<T, ORDER>(u + F2 + col, y, ny, nx);
-      at[1] = a.invx * dsum_c2<T, ORDER>(u + row, a.c2f ? a.c2f + row : nullptr, a.c2c, x, nx, 1);
-      at[2] = a.invy * dsum_c2<T, ORDER>(u + col, a.c2f ? a.c2f + col : nullptr, a.c2c, y, ny, nx);
+      at[0] = a.invx * dsum32<T, ORDER>(ux, idx, x, nx, 1) +
+              a.invy * dsum32<T, ORDER>(uy, idx, y, ny, snx);
+      at[1] = a.invx * dsum_c2_32<T, ORDER>(up, c2f, a.c2c, idx, x, nx, 1);
+      at[2] = a.invy * dsum_c2_32<T, ORDER>(up, c2f, a.c2c, idx, y, ny, snx);
       at[0] += a.invz * sb;
       at[3] = a.invz * sa;
       T dv = T(0);
@@ -243,38 +266,38 @@ __global__ __launch_bounds__(256) void adj_march3d(const AdjArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < R; ++k)
           sl += Fd<ORDER>::template w<T>(k) * (ql[R + 1 + k] - ql[R - 1 - k]);
-        T d = a.invx * dsum<T, ORDER>(lv + F1 + row, x, nx, 1) +
-              a.invy * dsum<T, ORDER>(lv + F2 + col, y, ny, nx);
-        d += a.invz * sl;
-        dv = -d;
+        T dd = a.invx * dsum32<T, ORDER>(lx, idx, x, nx, 1) +
+               a.invy * dsum32<T, ORDER>(ly, idx, y, ny, snx);
+        dd += a.invz * sl;
+        dv = -dd;
       }
       if constexpr (FIRST) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int64_t e = base + q * F1 + idx;
-          const T yb = a.ybar[e];
-          a.P[e] = ch * yb + h2 * (cq * at[q]);
-          a.Q[e] = ch * yb;
+          const int64_t fo = base + q * F1;
+          const T yb = a.ybar[fo + idx];
+          a.P[fo + idx] = ch * yb + h2 * (cq * at[q]);
+          a.Q[fo + idx] = ch * yb;
         }
         if (wantg)
           a.grad[idx] += 2.0 * a.h * ((double)cq * (double)a.ybar[base + idx]) * (double)dv;
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int64_t e = base + q * F1 + idx;
-          const T qn = a.Q[e] + h2 * at[q];
+          const int64_t fo = base + q * F1;
+          const T qn = a.Q[fo + idx] + h2 * at[q];
           if (!a.last) {
-            a.Q[e] = qn;
+            a.Q[fo + idx] = qn;
           } else {
             const double l1 = (double)qn;
-            const double v0 = l1 + (double)a.P[e];
+            const double v0 = l1 + (double)a.P[fo + idx];
             const double f0 = a.h * l1;
             if (a.first_seq) {
-              a.yacc[e] = v0;
-              a.facc[e] = f0;
+              a.yacc[fo + idx] = v0;
+              a.facc[fo + idx] = f0;
             } else {
-              a.yacc[e] += v0;
-              a.facc[e] += f0;
+              a.yacc[fo + idx] += v0;
+              a.facc[fo + idx] += f0;
             }
           }
         }

@@ -212,7 +212,9 @@ __global__ __launch_bounds__(256) void lf_march2d(const StepArgs<T> a) {
 // (x, y) column keeping the planes z-R..z+R of p and v_z in registers (the
 // z-derivatives), while the x- and y-derivatives read the current plane
 // (its rows are shared by the neighbouring blocks, which march in step).
-// Same arithmetic, in the same order, as lf_kernel.
+// Same arithmetic, in the same order, as lf_kernel.  (64-bit addressing:
+// measured faster here than 32-bit offsets, which raise the occupancy and
+// with it the L2 working set.)
 template <typename T, int ORDER, int TZ, bool NT>
 __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
   constexpr int R = Fd<ORDER>::R;
@@ -285,6 +287,76 @@ __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
         if (d.mode & MODE_FINAL) store<NT>(a.yout + e, (T)v);
         else store<NT>(a.acc + e, v);
       }
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+      pw[k] = pw[k + 1];
+      vw[k] = vw[k + 1];
+    }
+  }
+}
+
+// The shared first evaluation and the forward-Euler steps of every
+// sequence, 3-D, in the z-marching layout of lf_march3d.  Same arithmetic,
+// in the same order, as first_kernel.
+template <typename T, int ORDER, int TZ>
+__global__ __launch_bounds__(256) void first_march3d(const FirstArgs<T> a) {
+  constexpr int R = Fd<ORDER>::R;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int ntx = (nx + 63) >> 6, nty = (ny + 3) >> 2;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx;
+  const int ty = (tile / ntx) % nty;
+  const int tz = tile / (ntx * nty);
+  const int x = tx * 64 + (threadIdx.x & 63);
+  const int y = ty * 4 + (threadIdx.x >> 6);
+  const int z0 = tz * TZ;
+  if (x >= nx || y >= ny || z0 >= nz) return;
+  const int64_t rhs = blockIdx.z;
+  const int64_t base = rhs * a.g.state;
+  const int64_t F1 = a.g.field;
+  const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+  const uint32_t pil = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
+  const T* __restrict__ cp = a.y0 + base;
+  const T* __restrict__ cvx = cp + F1;
+  const T* __restrict__ cvy = cp + 2 * F1;
+  const T* __restrict__ cvz = cp + 3 * F1;
+  T pw[2 * R + 1], vw[2 * R + 1];
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {
+    const uint32_t e = (uint32_t)wrap(z0 - R + k, nz) * plane + pil;
+    pw[k] = cp[e];
+    vw[k] = cvz[e];
+  }
+  const int zend = min(z0 + TZ, nz);
+  for (int z = z0; z < zend; ++z) {
+    {
+      const uint32_t e = (uint32_t)wrap(z + R, nz) * plane + pil;
+      pw[2 * R] = cp[e];
+      vw[2 * R] = cvz[e];
+    }
+    const uint32_t idx = (uint32_t)z * plane + pil;
+    T szp = T(0), szv = T(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      szp += Fd<ORDER>::template w<T>(k) * (pw[R + 1 + k] - pw[R - 1 - k]);
+      szv += Fd<ORDER>::template w<T>(k) * (vw[R + 1 + k] - vw[R - 1 - k]);
+    }
+    const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
+    const T dvx = a.invx * dsum32<T, ORDER>(cvx, idx, x, nx, 1);
+    const T dvy = a.invy * dsum32<T, ORDER>(cvy, idx, y, ny, (uint32_t)nx);
+    const T dvz = a.invz * szv;
+    T f[4];
+    f[0] = -(c2 * ((dvx + dvy) + dvz));
+    f[1] = -(a.invx * dsum32<T, ORDER>(cp, idx, x, nx, 1));
+    f[2] = -(a.invy * dsum32<T, ORDER>(cp, idx, y, ny, (uint32_t)nx));
+    f[3] = -(a.invz * szp);
+    if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
+    const T v0[4] = {pw[R], cvx[idx], cvy[idx], vw[R]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t fo = base + q * F1;
+      for (int j = 0; j < a.nseq; ++j) a.out[j][fo + idx] = v0[q] + a.h[j] * f[q];
     }
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) {

@@ -245,8 +245,10 @@ void fill_geometry(const gbs_plan* P, Geometry& g, T& c2c, const T*& c2f, T& ix,
 
 int resolve_variant(const gbs_plan* P) {
   if (P->variant != GBS_VARIANT_AUTO) return P->variant;
-  if (P->prob.op == GBS_ACOUSTIC2D) return GBS_VARIANT_TEMPORAL;
-  if (P->prob.op == GBS_ACOUSTIC3D) return GBS_VARIANT_MARCH8;
+  if (P->prob.op == GBS_ACOUSTIC2D) return GBS_VARIANT_TEMPORAL_S5;
+  // the z-marching kernels index a field with 32-bit element offsets
+  if (P->prob.op == GBS_ACOUSTIC3D)
+    return P->field < (int64_t(1) << 31) ? GBS_VARIANT_MARCH8 : GBS_VARIANT_FLAT;
   return GBS_VARIANT_FLAT;
 }
 
@@ -422,6 +424,22 @@ void launch_march3d(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gz) {
 }
 
 template <typename T, int ORDER, int OP>
+void launch_first(gbs_plan* P, const FirstArgs<T>& fa, unsigned gx, unsigned gz) {
+  if constexpr (OP == OP_AC3D) {
+    const int v = resolve_variant(P);
+    if (v == GBS_VARIANT_MARCH8 || v == GBS_VARIANT_MARCH16) {
+      const int ntx = (int)((P->prob.n[0] + 63) / 64);
+      const int nty = (int)((P->prob.n[1] + 3) / 4);
+      const int ntz = (int)((P->prob.n[2] + 63) / 64);
+      hipLaunchKernelGGL((first_march3d<T, ORDER, 64>), dim3(ntx * nty * ntz, 1, gz), dim3(256), 0,
+                         P->stream, fa);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((first_kernel<T, ORDER, OP>), dim3(gx, 1, gz), dim3(256), 0, P->stream, fa);
+}
+
+template <typename T, int ORDER, int OP>
 void launch_lf(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gx, unsigned gz) {
   if constexpr (OP == OP_AC3D) {
     switch (resolve_variant(P)) {
@@ -481,7 +499,7 @@ int run(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
       ev = &next_event(P->first_ev, P->first_used);
       hipEventRecord(ev->a, P->stream);
     }
-    hipLaunchKernelGGL((first_kernel<T, ORDER, OP>), dim3(gx, 1, gz), dim3(block), 0, P->stream, fa);
+    launch_first<T, ORDER, OP>(P, fa, gx, gz);
     if (ev) hipEventRecord(ev->b, P->stream);
     for (int s = 1; s <= P->nmax; ++s) {
       int n = 0;
@@ -669,6 +687,8 @@ extern "C" int gbs_plan_set_variant(gbs_plan* P, int32_t variant) {
     return fail(GBS_EINVAL, "unknown variant %d", variant);
   const bool march3d = P->prob.op == GBS_ACOUSTIC3D &&
                        (variant == GBS_VARIANT_MARCH8 || variant == GBS_VARIANT_MARCH16);
+  if (march3d && P->field >= (int64_t(1) << 31))
+    return fail(GBS_EUNSUPPORTED, "the 3-D marching kernels need fields of fewer than 2^31 points");
   if (variant >= GBS_VARIANT_MARCH8 && variant != GBS_VARIANT_PLAIN && !march3d &&
       P->prob.op != GBS_ACOUSTIC2D)
     return fail(GBS_EUNSUPPORTED, "this variant is not built for this operator");
@@ -699,8 +719,9 @@ extern "C" int gbs_plan_autotune(gbs_plan* P, const void* y_in, void* y_out, int
     return GBS_OK;
   }
   const int variants[] = {GBS_VARIANT_TEMPORAL, GBS_VARIANT_TEMPORAL4, GBS_VARIANT_TEMPORAL_S5,
-                          GBS_VARIANT_TEMPORAL_WG4, GBS_VARIANT_TEMPORAL_WG8};
-  const int bands[] = {32, 64, 128};
+                          GBS_VARIANT_TEMPORAL_S6, GBS_VARIANT_TEMPORAL_WG4,
+                          GBS_VARIANT_TEMPORAL_WG8};
+  const int bands[] = {32, 64, 96, 128};
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return fail(GBS_EDEVICE, "creating events failed");
@@ -708,7 +729,8 @@ extern "C" int gbs_plan_autotune(gbs_plan* P, const void* y_in, void* y_out, int
   int bv = P->variant, bb = P->band;
   int st = GBS_OK;
   for (int v : variants) {
-    if (P->prob.fd_order == 8 && (v == GBS_VARIANT_TEMPORAL4 || v == GBS_VARIANT_TEMPORAL_S5))
+    if (P->prob.fd_order == 8 && (v == GBS_VARIANT_TEMPORAL4 || v == GBS_VARIANT_TEMPORAL_S5 ||
+                                  v == GBS_VARIANT_TEMPORAL_S6))
       continue;
     for (int band : bands) {
       P->variant = v;
@@ -1602,7 +1624,7 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
     fa.out[0] = L[1];
     fa.h[0] = (T)h;
     fa.amp = P->nsrc ? ricker(t0, P->f0, P->delay) : 0.0;
-    hipLaunchKernelGGL((first_kernel<T, ORDER, OP>), dim3(gx, 1, gz), dim3(256), 0, s, fa);
+    launch_first<T, ORDER, OP>(P, fa, gx, gz);
     for (int st = 1; st <= N - 1; ++st) {
       SeqDesc<T>& d = sa.seq[0];
       d.cur = L[st];

@@ -49,6 +49,24 @@ __device__ __forceinline__ T dsum(const T* __restrict__ base, int i, int n, int6
   return s;
 }
 
+// dsum for a field addressed by 32-bit element indices from a uniform base
+// pointer (fields of fewer than 2^31 points): c is the centre's index, i its
+// coordinate along the axis (period n), s the axis stride.  Same products
+// and sums, in the same order, as dsum; the narrow offsets let loads use a
+// scalar base and one 32-bit register per address.
+template <typename T, int ORDER>
+__device__ __forceinline__ T dsum32(const T* __restrict__ f, uint32_t c, int i, int n,
+                                    uint32_t s) {
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < Fd<ORDER>::R; ++k) {
+    const uint32_t up = c + (uint32_t)(wrap(i + k + 1, n) - i) * s;
+    const uint32_t dn = c + (uint32_t)(wrap(i - k - 1, n) - i) * s;
+    acc += Fd<ORDER>::template w<T>(k) * (f[up] - f[dn]);
+  }
+  return acc;
+}
+
 // Mode bits of one sequence in one leap-frog launch.
 enum : int32_t {
   MODE_LAST = 1,    // s == N_j: average, combine, no level written

@@ -144,9 +144,13 @@ def test_algorithmic_bytes_of_both_schedules():
     h = B.plan_create(pr, sc, 1e-4, FAKE_WS, nb)
     try:
         out = [ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()]
+        v = ctypes.c_int32()
+        B.check(B.lib().gbs_plan_get_variant(h, ctypes.byref(v)))
+        assert v.value == B.VARIANT_TEMPORAL_S5                  # the 2-D default
+        B.check(B.lib().gbs_plan_set_variant(h, B.VARIANT_TEMPORAL))
         B.check(B.lib().gbs_plan_algorithmic_bytes(h, *[ctypes.byref(x) for x in out]))
         pts = 64 * 32
-        # default (temporally blocked, at most 7 evaluations per pass): N = 2, 4, 6 take
+        # temporally blocked, at most 7 evaluations per pass: N = 2, 4, 6 take
         # one pass (read y0, write y*), N = 8, 10, 12 two (y0 -> 2 levels -> y*)
         assert out[0].value == pts * (3 * (24 + 24) + 3 * (24 + 48 + 48 + 24))
         assert out[1].value == 2
