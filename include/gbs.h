@@ -205,7 +205,9 @@ int gbs_step(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void*
  * be contracted differently).
  * gbs_plan_get_variant returns the variant AUTO resolves to.
  * gbs_plan_set_band sets the rows per band of the temporally blocked
- * passes (default 64).
+ * passes; 0 (the default) lets the library choose per launch from the
+ * launch's wavefront count and the GPU's resident wavefronts (taller bands
+ * for launches with few sequences).
  */
 enum {
   GBS_VARIANT_AUTO = 0,
@@ -229,7 +231,7 @@ int gbs_plan_get_variant(const gbs_plan* plan, int32_t* variant);
 /*
  * gbs_plan_autotune — the project's own tuner: times every temporally
  * blocked variant (those built for the plan's stencil order) at 32, 64, 96
- * and 128 rows per band, macro_steps macro steps each from y_in into y_out
+ * and 128 rows per band and with the per-launch choice (0), macro_steps macro steps each from y_in into y_out
  * (device buffers of one state, may be the same; y_out is overwritten), on
  * the plan's stream, and keeps the fastest.  Operators other than the 2-D
  * acoustic one have a single form: the call returns it unchanged.

@@ -76,7 +76,7 @@ struct gbs_plan {
   // leap-frog kernel variant (GBS_VARIANT_*) and rows per band of the
   // temporally blocked passes
   int variant = 0;
-  int band = 64;
+  int band = 0;            // 0: chosen per launch
   // temporally blocked layout: per sequence two pairs of levels
   void* pair[GBS_MAX_SEQ][2][2];
   // timing
@@ -325,6 +325,42 @@ int make_schedule(const int32_t* steps, int k, int G, int R, int wpg, PassSchedu
   return GBS_OK;
 }
 
+// Wavefronts the GPU holds at once for a pass kernel (occupancy x CUs).
+template <typename K>
+int resident_waves(K kernel, int block) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+      per_cu < 1 || cus < 1)
+    return 0;
+  return per_cu * cus * (block / 64);
+}
+
+// Rows per band of one round of passes when the plan leaves it automatic
+// (band 0): the candidate minimising (rounds of resident wavefronts) x
+// (rows one wavefront steps through, band + g (R + S)) for the round's
+// largest g.  Few sequences in a round (its later rounds) get taller bands,
+// so that the round does not end in a partly filled wave of wavefronts.
+int band_for_round(const gbs_plan* P, int total_strips, int gmax, int R, int S, int slots) {
+  if (P->band > 0) return P->band;
+  const int ny = (int)P->prob.n[1];
+  if (slots <= 0) return 64;
+  const int cand[] = {32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 192, 256};
+  int best = 64;
+  double best_t = 1e300;
+  for (int b : cand) {
+    const long waves = (long)total_strips * ((ny + b - 1) / b);
+    const long rounds = (waves + slots - 1) / slots;
+    const double t = (double)rounds * (double)(std::min(b, ny) + gmax * (R + S));
+    if (t < best_t * (1.0 - 1e-9)) {
+      best_t = t;
+      best = b;
+    }
+  }
+  return best;
+}
+
 template <typename T, int ORDER, int G, bool SKEW1, int WPG>
 int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   constexpr int R = Fd<ORDER>::R;
@@ -338,9 +374,13 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
   pa.c2c = c2c;
   pa.src_dev = P->src_dev;
-  pa.band = P->band;
-  pa.nbands = (int)((P->prob.n[1] + P->band - 1) / P->band);
   const int nx = (int)P->prob.n[0];
+  constexpr int S = SKEW1 ? R + 1 : R;
+  static const int slots_c = resident_waves(pass2d<T, ORDER, G, SKEW1, WPG, false>,
+                                            WPG > 1 ? 64 * WPG : 256);
+  static const int slots_v = resident_waves(pass2d<T, ORDER, G, SKEW1, WPG, true>,
+                                            WPG > 1 ? 64 * WPG : 256);
+  const int slots = (P->prob.c2_field ? slots_v : slots_c) / WPG;   // units of WPG wavefronts
   CombineArgs<T> ca;
   std::memset(&ca, 0, sizeof(ca));
   ca.k = P->k;
@@ -378,6 +418,15 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         maxs = std::max(maxs, d.strips);
       }
       pa.max_strips = maxs;
+      {
+        int strips = 0, gmax = 0;
+        for (int i = 0; i < n; ++i) {
+          strips += pa.seq[i].strips;
+          gmax = std::max(gmax, pa.seq[i].g);
+        }
+        pa.band = band_for_round(P, strips, gmax, R, S, slots);
+        pa.nbands = (int)((P->prob.n[1] + pa.band - 1) / pa.band);
+      }
       const unsigned waves = (unsigned)maxs * pa.nbands;
       EventPair* ev = nullptr;
       if (P->timing) {
@@ -698,7 +747,7 @@ extern "C" int gbs_plan_set_variant(gbs_plan* P, int32_t variant) {
 
 extern "C" int gbs_plan_set_band(gbs_plan* P, int32_t rows) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
-  if (rows < 1 || rows > (1 << 20)) return fail(GBS_EINVAL, "rows per band out of range");
+  if (rows < 0 || rows > (1 << 20)) return fail(GBS_EINVAL, "rows per band out of range");
   P->band = rows;
   return GBS_OK;
 }
@@ -721,7 +770,7 @@ extern "C" int gbs_plan_autotune(gbs_plan* P, const void* y_in, void* y_out, int
   const int variants[] = {GBS_VARIANT_TEMPORAL, GBS_VARIANT_TEMPORAL4, GBS_VARIANT_TEMPORAL_S5,
                           GBS_VARIANT_TEMPORAL_S6, GBS_VARIANT_TEMPORAL_WG4,
                           GBS_VARIANT_TEMPORAL_WG8};
-  const int bands[] = {32, 64, 96, 128};
+  const int bands[] = {0, 32, 64, 96, 128};
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return fail(GBS_EDEVICE, "creating events failed");
@@ -1368,9 +1417,11 @@ int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX
   fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
   pa.c2c = c2c;
   pa.src_dev = P->src_dev;
-  pa.band = P->band;
-  pa.nbands = (int)((P->prob.n[1] + P->band - 1) / P->band);
   const int nx = (int)P->prob.n[0];
+  constexpr int S = SKEW1 ? R + 1 : R;
+  static const int slots_c = resident_waves(pass2d<T, ORDER, G, SKEW1, 1, false>, 256);
+  static const int slots_v = resident_waves(pass2d<T, ORDER, G, SKEW1, 1, true>, 256);
+  const int slots = P->prob.c2_field ? slots_v : slots_c;
   for (int rr = 0; rr < sch.nrounds; ++rr) {
     int n = 0, maxs = 0;
     for (int r = 0; r < P->k; ++r) {
@@ -1395,6 +1446,15 @@ int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX
       maxs = std::max(maxs, d.strips);
     }
     pa.max_strips = maxs;
+    {
+      int strips = 0, gmax = 0;
+      for (int i = 0; i < n; ++i) {
+        strips += pa.seq[i].strips;
+        gmax = std::max(gmax, pa.seq[i].g);
+      }
+      pa.band = band_for_round(P, strips, gmax, R, S, slots);
+      pa.nbands = (int)((P->prob.n[1] + pa.band - 1) / pa.band);
+    }
     const unsigned blocks = ((unsigned)maxs * pa.nbands + 3) / 4;
     const dim3 grid(blocks, n, P->prob.n_rhs), blk(256);
     if (P->prob.c2_field)
@@ -1491,9 +1551,10 @@ int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* t
   pa.c2c = c2c;
   pa.src_dev = P->src_dev;
   pa.zstride = (int64_t)elems;
-  pa.band = P->band;
-  pa.nbands = (int)((P->prob.n[1] + P->band - 1) / P->band);
   const int nx = (int)P->prob.n[0];
+  static const int slots_c = resident_waves(adj_pass2d<T, G, false>, 256);
+  static const int slots_v = resident_waves(adj_pass2d<T, G, true>, 256);
+  const int slots = P->prob.c2_field ? slots_v : slots_c;
   for (int rr = 0; rr < sch.nrounds; ++rr) {
     int n = 0, maxs = 0;
     for (int r = 0; r < P->k; ++r) {
@@ -1525,6 +1586,15 @@ int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* t
       maxs = std::max(maxs, d.strips);
     }
     pa.max_strips = maxs;
+    {
+      int strips = 0, gmax = 0;
+      for (int q2 = 0; q2 < n; ++q2) {
+        strips += pa.seq[q2].strips;
+        gmax = std::max(gmax, pa.seq[q2].g);
+      }
+      pa.band = band_for_round(P, strips, gmax, R, R, slots);
+      pa.nbands = (int)((P->prob.n[1] + pa.band - 1) / pa.band);
+    }
     const unsigned blocks = ((unsigned)maxs * pa.nbands + 3) / 4;
     const dim3 grid(blocks, n, P->prob.n_rhs), blk(256);
     if (P->prob.c2_field)

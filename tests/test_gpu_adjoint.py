@@ -190,7 +190,7 @@ def test_adjoint_3d_march_matches_flat(dtype, tol):
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
-@pytest.mark.parametrize("band", [64, 19])
+@pytest.mark.parametrize("band", [64, 19, 0])
 def test_blocked_adjoint_matches_streaming(dtype, tol, band):
     # the temporally blocked adjoint (levels regenerated backwards, Psi
     # variables) against the streaming one (levels stored), two right-hand
