@@ -427,8 +427,10 @@ def main():
             B.check(B.lib().gbs_plan_set_band(plan.handle, args.band))
     else:
         # the library's own autotuner picks the blocked variant and band
-        # (untimed; it writes only into `out`)
-        tuned = plan.autotune(y, out, macro_steps=5)
+        # (untimed; it writes only into `out`).  One lane: the passes of a
+        # macro step run one launch at a time, so that each launch's HIP-event
+        # duration (the roofline figure) is not shared with a concurrent one.
+        tuned = plan.autotune(y, out, macro_steps=5, lanes=1)
 
     plan.step(y, out, n_macro=args.warmup)
     torch.cuda.synchronize()
@@ -469,7 +471,8 @@ def main():
         config=dict(workload=cfg["name"], grid=[n, n], fields=3, fd_order=4,
                     scheme_order=8, sequences=steps, evals_per_macro_step=1 + sum(steps),
                     H=cfg["H"], macro_steps_timed=args.steps, kernel_variant=variant,
-                    autotuned=dict(variant=tuned[0], band=tuned[1]) if tuned else None),
+                    autotuned=dict(variant=tuned[0], band=tuned[1], lanes=tuned[2]) if tuned
+                    else None),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                       traffic_bytes_per_launch=measured, kernel=kstep,

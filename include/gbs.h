@@ -229,16 +229,32 @@ int gbs_plan_set_band(gbs_plan* plan, int32_t rows);
 int gbs_plan_get_variant(const gbs_plan* plan, int32_t* variant);
 
 /*
+ * gbs_plan_set_lanes — lanes (1..4, default 1): the temporally blocked
+ * passes of one macro step are spread over this many HIP streams — the
+ * plan's stream and lanes - 1 streams the plan creates (default priority) —
+ * with the sequences folded in pairs by ascending N (longest with shortest,
+ * Sect. 3.6) and pair i on lane i mod lanes; the lanes start after all
+ * earlier work on the plan's stream and are joined back into it before the
+ * combination, so callers see every result ordered on the plan's stream.
+ * Lanes let a launch with few sequences share the GPU with another lane's
+ * launch instead of ending in a partly filled wave of wavefronts.  Other
+ * variants ignore it.
+ */
+int gbs_plan_set_lanes(gbs_plan* plan, int32_t lanes);
+
+/*
  * gbs_plan_autotune — the project's own tuner: times every temporally
  * blocked variant (those built for the plan's stencil order) at 32, 64, 96
- * and 128 rows per band and with the per-launch choice (0), macro_steps macro steps each from y_in into y_out
- * (device buffers of one state, may be the same; y_out is overwritten), on
- * the plan's stream, and keeps the fastest.  Operators other than the 2-D
- * acoustic one have a single form: the call returns it unchanged.
- * variant_out and band_out are nullable.  Synchronises the plan's stream.
+ * and 128 rows per band and with the per-launch choice (0), on 1, 2 and 3
+ * lanes (or, if *lanes_io > 0 on entry, on that many only), macro_steps
+ * macro steps each from y_in into y_out (device buffers of one state, may be
+ * the same; y_out is overwritten), on the plan's stream, and keeps the
+ * fastest.  Operators other than the 2-D acoustic one have a single form:
+ * the call returns it unchanged.  variant_out, band_out and lanes_io (host,
+ * on return the lanes chosen) are nullable.  Synchronises the plan's stream.
  */
 int gbs_plan_autotune(gbs_plan* plan, const void* y_in, void* y_out, int32_t macro_steps,
-                      int32_t* variant_out, int32_t* band_out);
+                      int32_t* variant_out, int32_t* band_out, int32_t* lanes_io);
 
 /*
  * gbs_plan_set_timing — enabled != 0: every kernel launch is bracketed by HIP

@@ -77,7 +77,8 @@ def lib():
             "gbs_plan_set_timing": [vp, i32],
             "gbs_plan_set_variant": [vp, i32],
             "gbs_plan_get_variant": [vp, P(i32)],
-            "gbs_plan_autotune": [vp, vp, vp, i32, P(i32), P(i32)],
+            "gbs_plan_autotune": [vp, vp, vp, i32, P(i32), P(i32), P(i32)],
+            "gbs_plan_set_lanes": [vp, i32],
             "gbs_plan_set_band": [vp, i32],
             "gbs_plan_get_timing": [vp, P(dbl), P(i64), P(dbl), P(i64)],
             "gbs_plan_updates_per_macro_step": [vp, P(dbl)],

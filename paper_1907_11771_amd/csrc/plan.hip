@@ -51,6 +51,8 @@ struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
+constexpr int GBS_MAX_LANES = 4;
+
 struct gbs_plan {
   gbs_problem prob;
   int k = 0;
@@ -79,6 +81,13 @@ struct gbs_plan {
   int band = 0;            // 0: chosen per launch
   // temporally blocked layout: per sequence two pairs of levels
   void* pair[GBS_MAX_SEQ][2][2];
+  // the blocked passes of one macro step spread over `lanes` streams (the
+  // plan's stream and lanes - 1 streams of its own), joined before the
+  // combination
+  int lanes = 1;
+  hipStream_t lane_stream[GBS_MAX_LANES] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[GBS_MAX_LANES] = {};
   // timing
   bool timing = false;
   std::vector<EventPair> lf_ev, first_ev;
@@ -391,15 +400,28 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
     ca.c[r] = P->w[j];
     ca.ystar[r] = (const double*)P->pair[j][(npass[j] - 1) % 2 == 0 ? 0 : 1][0];
   }
+  // lanes: sequences folded in pairs by ascending N (longest with shortest,
+  // as the paper folds sequences onto cores, Sect. 3.6), pair i on lane
+  // i mod L; each lane runs its passes on its own stream
+  const int L = std::max(1, std::min(P->lanes, P->k));
+  int lane_of[GBS_MAX_SEQ];
+  for (int r = 0; r < P->k; ++r) lane_of[r] = std::min(r, P->k - 1 - r) % L;
+  const int lane_slots = std::max(1, slots / L);
   for (int m = 0; m < n_macro; ++m) {
     const double t = t0 + m * P->H;
     const T* y0 = m == 0 ? yin : yout;
+    if (L > 1) {
+      hipEventRecord(P->ev_fork, P->stream);
+      for (int l = 1; l < L; ++l) hipStreamWaitEvent(P->lane_stream[l], P->ev_fork, 0);
+    }
+    for (int l = 0; l < L; ++l)
     for (int rr = 0; rr < sch.nrounds; ++rr) {
+      hipStream_t ls = l == 0 ? P->stream : P->lane_stream[l];
       int n = 0, maxs = 0;
       for (int r = 0; r < P->k; ++r) {
         const int j = P->order[r];
         const int q = rr - sch.round0[j];
-        if (q < 0 || q >= npass[j]) continue;
+        if (lane_of[r] != l || q < 0 || q >= npass[j]) continue;
         PassSeq<T>& d = pa.seq[n++];
         const double h = P->H / P->steps[j];
         int s0 = 0;             // the pass's input level is y_{s0}: s0 = evaluations so far
@@ -417,6 +439,7 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
           d.amp[e] = P->nsrc ? ricker(t + (s0 + e) * h, P->f0, P->delay) : 0.0;
         maxs = std::max(maxs, d.strips);
       }
+      if (n == 0) continue;
       pa.max_strips = maxs;
       {
         int strips = 0, gmax = 0;
@@ -424,22 +447,28 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
           strips += pa.seq[i].strips;
           gmax = std::max(gmax, pa.seq[i].g);
         }
-        pa.band = band_for_round(P, strips, gmax, R, S, slots);
+        pa.band = band_for_round(P, strips, gmax, R, S, L > 1 ? lane_slots : slots);
         pa.nbands = (int)((P->prob.n[1] + pa.band - 1) / pa.band);
       }
       const unsigned waves = (unsigned)maxs * pa.nbands;
       EventPair* ev = nullptr;
       if (P->timing) {
         ev = &next_event(P->lf_ev, P->lf_used);
-        hipEventRecord(ev->a, P->stream);
+        hipEventRecord(ev->a, ls);
       }
       const unsigned blocks = WPG > 1 ? waves : (waves + 3) / 4;
       const dim3 grid(blocks, n, P->prob.n_rhs), blk(WPG > 1 ? 64 * WPG : 256);
       if (P->prob.c2_field)
-        hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, true>), grid, blk, 0, P->stream, pa);
+        hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, true>), grid, blk, 0, ls, pa);
       else
-        hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, false>), grid, blk, 0, P->stream, pa);
-      if (ev) hipEventRecord(ev->b, P->stream);
+        hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, false>), grid, blk, 0, ls, pa);
+      if (ev) hipEventRecord(ev->b, ls);
+    }
+    if (L > 1) {
+      for (int l = 1; l < L; ++l) {
+        hipEventRecord(P->ev_join[l], P->lane_stream[l]);
+        hipStreamWaitEvent(P->stream, P->ev_join[l], 0);
+      }
     }
     EventPair* ev = nullptr;
     if (P->timing) {
@@ -752,6 +781,25 @@ extern "C" int gbs_plan_set_band(gbs_plan* P, int32_t rows) {
   return GBS_OK;
 }
 
+extern "C" int gbs_plan_set_lanes(gbs_plan* P, int32_t lanes) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  if (lanes < 1 || lanes > GBS_MAX_LANES) return fail(GBS_EINVAL, "lanes must be 1..%d", GBS_MAX_LANES);
+  if (lanes > 1 && !P->ev_fork) {
+    if (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess)
+      return fail(GBS_EDEVICE, "creating an event failed");
+  }
+  for (int l = 1; l < lanes; ++l) {
+    if (!P->lane_stream[l] &&
+        hipStreamCreateWithFlags(&P->lane_stream[l], hipStreamNonBlocking) != hipSuccess)
+      return fail(GBS_EDEVICE, "creating a stream failed");
+    if (!P->ev_join[l] &&
+        hipEventCreateWithFlags(&P->ev_join[l], hipEventDisableTiming) != hipSuccess)
+      return fail(GBS_EDEVICE, "creating an event failed");
+  }
+  P->lanes = lanes;
+  return GBS_OK;
+}
+
 extern "C" int gbs_plan_get_variant(const gbs_plan* P, int32_t* variant) {
   if (!P || !variant) return fail(GBS_EINVAL, "null argument");
   *variant = resolve_variant(P);
@@ -759,44 +807,54 @@ extern "C" int gbs_plan_get_variant(const gbs_plan* P, int32_t* variant) {
 }
 
 extern "C" int gbs_plan_autotune(gbs_plan* P, const void* y_in, void* y_out, int32_t macro_steps,
-                                 int32_t* variant_out, int32_t* band_out) {
+                                 int32_t* variant_out, int32_t* band_out, int32_t* lanes_io) {
   if (!P || !y_in || !y_out || macro_steps < 1) return fail(GBS_EINVAL, "bad arguments");
   if (P->prob.op != GBS_ACOUSTIC2D) {
     // one kernel form for the other operators
     if (variant_out) *variant_out = resolve_variant(P);
     if (band_out) *band_out = P->band;
+    if (lanes_io) *lanes_io = P->lanes;
     return GBS_OK;
   }
   const int variants[] = {GBS_VARIANT_TEMPORAL, GBS_VARIANT_TEMPORAL4, GBS_VARIANT_TEMPORAL_S5,
                           GBS_VARIANT_TEMPORAL_S6, GBS_VARIANT_TEMPORAL_WG4,
                           GBS_VARIANT_TEMPORAL_WG8};
   const int bands[] = {0, 32, 64, 96, 128};
+  const int fixed = lanes_io ? *lanes_io : 0;
+  if (fixed < 0 || fixed > GBS_MAX_LANES) return fail(GBS_EINVAL, "lanes must be 0..%d", GBS_MAX_LANES);
+  std::vector<int> lane_counts = {1, 2, 3};
+  if (fixed > 0) lane_counts = {fixed};
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return fail(GBS_EDEVICE, "creating events failed");
   float best = 1e30f;
-  int bv = P->variant, bb = P->band;
+  int bv = P->variant, bb = P->band, bl = P->lanes;
   int st = GBS_OK;
-  for (int v : variants) {
-    if (P->prob.fd_order == 8 && (v == GBS_VARIANT_TEMPORAL4 || v == GBS_VARIANT_TEMPORAL_S5 ||
-                                  v == GBS_VARIANT_TEMPORAL_S6))
-      continue;
-    for (int band : bands) {
-      P->variant = v;
-      P->band = band;
-      st = gbs_step(P, 0.0, 1, y_in, y_out);              // warm-up
-      if (st) break;
-      hipEventRecord(a, P->stream);
-      st = gbs_step(P, 0.0, macro_steps, y_in, y_out);
-      hipEventRecord(b, P->stream);
-      if (st) break;
-      if (hipEventSynchronize(b) != hipSuccess) {
-        st = fail(GBS_EDEVICE, "event sync failed");
-        break;
+  for (int lanes : lane_counts) {
+    st = gbs_plan_set_lanes(P, lanes);
+    if (st) break;
+    for (int v : variants) {
+      if (P->prob.fd_order == 8 && (v == GBS_VARIANT_TEMPORAL4 || v == GBS_VARIANT_TEMPORAL_S5 ||
+                                    v == GBS_VARIANT_TEMPORAL_S6))
+        continue;
+      for (int band : bands) {
+        P->variant = v;
+        P->band = band;
+        st = gbs_step(P, 0.0, 1, y_in, y_out);              // warm-up
+        if (st) break;
+        hipEventRecord(a, P->stream);
+        st = gbs_step(P, 0.0, macro_steps, y_in, y_out);
+        hipEventRecord(b, P->stream);
+        if (st) break;
+        if (hipEventSynchronize(b) != hipSuccess) {
+          st = fail(GBS_EDEVICE, "event sync failed");
+          break;
+        }
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        if (ms < best) { best = ms; bv = v; bb = band; bl = lanes; }
       }
-      float ms = 0;
-      hipEventElapsedTime(&ms, a, b);
-      if (ms < best) { best = ms; bv = v; bb = band; }
+      if (st) break;
     }
     if (st) break;
   }
@@ -804,9 +862,11 @@ extern "C" int gbs_plan_autotune(gbs_plan* P, const void* y_in, void* y_out, int
   hipEventDestroy(b);
   P->variant = bv;
   P->band = bb;
+  if (gbs_plan_set_lanes(P, bl) != GBS_OK && !st) st = GBS_EDEVICE;
   if (st) return st;
   if (variant_out) *variant_out = bv;
   if (band_out) *band_out = bb;
+  if (lanes_io) *lanes_io = bl;
   return GBS_OK;
 }
 
@@ -904,6 +964,14 @@ extern "C" int gbs_plan_updates_per_macro_step(const gbs_plan* P, double* update
 
 extern "C" int gbs_plan_destroy(gbs_plan* P) {
   if (!P) return GBS_OK;
+  for (int l = 1; l < GBS_MAX_LANES; ++l) {
+    if (P->lane_stream[l]) {
+      hipStreamSynchronize(P->lane_stream[l]);
+      hipStreamDestroy(P->lane_stream[l]);
+    }
+    if (P->ev_join[l]) hipEventDestroy(P->ev_join[l]);
+  }
+  if (P->ev_fork) hipEventDestroy(P->ev_fork);
   for (auto& e : P->lf_ev) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   for (auto& e : P->first_ev) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   delete P;

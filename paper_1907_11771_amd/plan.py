@@ -131,16 +131,23 @@ class GBSPlan:
     def set_variant(self, variant):
         B.check(B.lib().gbs_plan_set_variant(self.handle, int(variant)))
 
-    def autotune(self, y, out=None, macro_steps=5):
-        """Times the blocked variants and bands (gbs_plan_autotune) on a copy
-        of ``y`` and keeps the fastest; returns (variant, band)."""
+    def autotune(self, y, out=None, macro_steps=5, lanes=0):
+        """Times the blocked variants, bands and lane counts
+        (gbs_plan_autotune) from ``y`` into ``out`` (a scratch copy if None)
+        and keeps the fastest; ``lanes`` > 0 fixes the lane count.  Returns
+        (variant, band, lanes)."""
         self._check_state(y)
         scratch = y.clone() if out is None else out
         self._check_state(scratch)
-        v, b = ctypes.c_int32(), ctypes.c_int32()
+        v, b, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(int(lanes))
         B.check(B.lib().gbs_plan_autotune(self.handle, y.data_ptr(), scratch.data_ptr(),
-                                          int(macro_steps), ctypes.byref(v), ctypes.byref(b)))
-        return v.value, b.value
+                                          int(macro_steps), ctypes.byref(v), ctypes.byref(b),
+                                          ctypes.byref(l)))
+        return v.value, b.value, l.value
+
+    def set_lanes(self, lanes):
+        """Streams the blocked passes of a macro step are spread over (1..4)."""
+        B.check(B.lib().gbs_plan_set_lanes(self.handle, int(lanes)))
 
     def variant(self):
         out = ctypes.c_int32()

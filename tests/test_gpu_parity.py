@@ -244,10 +244,32 @@ def test_plan_autotune_keeps_a_blocked_variant_with_the_same_result():
     ref.set_variant(B.VARIANT_FLAT)
     want = ref.step(y0, n_macro=2).cpu().numpy()
     plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, c2_field=to_dev(cs ** 2), c_max=float(cs.max()))
-    v, band = plan.autotune(y0, macro_steps=2)
+    v, band, lanes = plan.autotune(y0, macro_steps=2)
+    assert lanes in (1, 2, 3)
     assert v in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
                  B.VARIANT_TEMPORAL_S6, B.VARIANT_TEMPORAL_WG4, B.VARIANT_TEMPORAL_WG8)
     assert band in (0, 32, 64, 96, 128)
     assert plan.variant() == v
     got = plan.step(y0, n_macro=2).cpu().numpy()
     assert rel_err(got, want) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_lanes_do_not_change_the_result(dtype):
+    # the blocked passes spread over 1..4 streams compute the same values
+    ny, nx = 150, 130
+    sch = schemes.ORDER8_K6
+    cs = fields.lognormal_speed((ny, nx), seed=8)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(nx, ny), 2,
+                           workloads.SIGMA_FD4)
+    y0 = to_dev(np.random.default_rng(9).standard_normal((2, 3, ny, nx)), dtype)
+    s = fields.ricker_source_2d(max(nx, ny), cells_per_wavelength=8.0)
+    outs = []
+    for lanes in (1, 2, 3, 4):
+        plan = lib_plan(B.ACOUSTIC2D, (nx, ny), sch, H, n_rhs=2, dtype=dtype,
+                        c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
+        plan.set_sources([0], [60 * nx + 70], [s["weight"] * 1e-4], s["f0"], s["delay"])
+        plan.set_lanes(lanes)
+        outs.append(plan.step(y0, t0=0.3 * s["delay"], n_macro=4))
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])

@@ -229,3 +229,16 @@ def test_stability_check_uses_the_exact_scheme_behind_rounded_weights():
     with pytest.raises(B.GBSError) as ei:
         B.plan_create(pr, sc, 1.01 * isb / rho, FAKE_WS, nb)
     assert ei.value.status == B.GBS_EUNSTABLE
+
+
+def test_lanes_validation_on_host():
+    steps, w = _cfg2()
+    pr = B.make_problem(B.ACOUSTIC2D, (64, 32))
+    sc = B.make_scheme(8, steps, w)
+    h = B.plan_create(pr, sc, 1e-4, FAKE_WS, B.workspace_bytes(pr, sc))
+    try:
+        for bad in (0, 5, -1):
+            assert B.lib().gbs_plan_set_lanes(h, bad) == B.GBS_EINVAL
+        B.check(B.lib().gbs_plan_set_lanes(h, 1))
+    finally:
+        B.plan_destroy(h)
