@@ -34,6 +34,12 @@ struct Fd<8> {
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// a mod n in [0, n) for any int a (n > 0)
+__device__ __forceinline__ int pmod(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
 // Sum_k W_k (u[i+k] - u[i-k]) along an axis with stride `stride` and
 // periodic length n, around the index `i` (0 <= i < n); `base` points at
 // element 0 of that line.

@@ -88,10 +88,6 @@ __device__ __forceinline__ T lane_dsum(T u) {
   return s;
 }
 
-__device__ __forceinline__ int pmod(int a, int n) {
-  int r = a % n;
-  return r < 0 ? r + n : r;
-}
 // r - d wrapped into [0, n) for 0 <= r < n, d >= 0 (wave-uniform operands)
 __device__ __forceinline__ int wrap_sub(int r, int d, int n) {
   r -= d;
