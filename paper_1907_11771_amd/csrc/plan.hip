@@ -1331,8 +1331,9 @@ extern "C" int gbs_batch_autotune(gbs_batch_plan* B, void* const* y, int32_t mac
                                   int32_t* variant_out, int32_t* band_out) {
   if (!B || !y || macro_steps < 1) return fail(GBS_EINVAL, "bad arguments");
   const int variants[] = {GBS_VARIANT_TEMPORAL, GBS_VARIANT_TEMPORAL4, GBS_VARIANT_TEMPORAL_S5,
-                          GBS_VARIANT_TEMPORAL_WG4, GBS_VARIANT_TEMPORAL_WG8};
-  const int bands[] = {32, 64, 128};
+                          GBS_VARIANT_TEMPORAL_S6, GBS_VARIANT_TEMPORAL_WG4,
+                          GBS_VARIANT_TEMPORAL_WG8};
+  const int bands[] = {32, 64, 96, 128};
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return fail(GBS_EDEVICE, "creating events failed");
@@ -1341,7 +1342,9 @@ extern "C" int gbs_batch_autotune(gbs_batch_plan* B, void* const* y, int32_t mac
   float best = 1e30f;
   int bv = B->variant, bb = B->band;
   for (int v : variants) {
-    if (B->fd_order == 8 && (v == GBS_VARIANT_TEMPORAL4 || v == GBS_VARIANT_TEMPORAL_S5)) continue;
+    if (B->fd_order == 8 && (v == GBS_VARIANT_TEMPORAL4 || v == GBS_VARIANT_TEMPORAL_S5 ||
+                             v == GBS_VARIANT_TEMPORAL_S6))
+      continue;
     for (int band : bands) {
       gbs_batch_set_variant(B, v, band);
       int st = gbs_batch_step(B, 1, y);                  // warm-up (and table upload)

@@ -37,7 +37,7 @@ def _states(dtype, seed=0):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("variant,band", [(B.VARIANT_TEMPORAL, 64), (B.VARIANT_TEMPORAL4, 30),
                                           (B.VARIANT_TEMPORAL_S5, 128), (B.VARIANT_TEMPORAL_WG4, 64),
-                                          (B.VARIANT_TEMPORAL_WG8, 48)])
+                                          (B.VARIANT_TEMPORAL_WG8, 48), (B.VARIANT_TEMPORAL_S6, 96)])
 def test_batch_equals_single_instances(dtype, variant, band):
     sch = schemes.ORDER8_K6
     steps, w, _ = scheme_weights(sch)
