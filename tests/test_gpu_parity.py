@@ -224,7 +224,11 @@ def test_acoustic2d_full_size_500_steps_vs_closed_form():
     steps, c = oracle_weights(cfg["scheme"])
     y0 = fields.acoustic2d_pulse_modes(n)
     plan = lib_plan(B.ACOUSTIC2D, (n, n), cfg["scheme"], cfg["H"])
-    out = plan.step(to_dev(y0[None]), n_macro=cfg["n_macro"])
+    y = to_dev(y0[None])
+    # the configuration bench.py times: autotuned on one lane
+    tuned = plan.autotune(y, torch.empty_like(y), macro_steps=5, lanes=1)
+    print("autotuned (variant, band, lanes)", tuned)
+    out = plan.step(y, n_macro=cfg["n_macro"])
     got = out.cpu().numpy()[0]
     want = SP.acoustic(y0, 1.0, cfg["H"], steps, c, cfg["n_macro"])
     errs = [rel_err(got[q], want[q]) if q == 0 else
