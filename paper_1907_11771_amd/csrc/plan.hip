@@ -1477,7 +1477,8 @@ constexpr int adj_pass_g() { return sizeof(T) == 8 ? 3 : 4; }
 // passes of the plan's forward form (G = 7) over N evaluations, the last
 // pass storing its last two levels.  pair_out[j] receives the pair.
 template <typename T, int G, bool SKEW1>
-int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX_SEQ][2]) {
+int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX_SEQ][2],
+                  const int* lane_of, int lane, int lanes, hipStream_t stream) {
   constexpr int ORDER = 4, R = 2;
   PassSchedule sch;
   int st = make_schedule(P->steps, P->k, G, R, 1, sch, false, 0);
@@ -1492,13 +1493,13 @@ int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX
   constexpr int S = SKEW1 ? R + 1 : R;
   static const int slots_c = resident_waves(pass2d<T, ORDER, G, SKEW1, 1, false>, 256);
   static const int slots_v = resident_waves(pass2d<T, ORDER, G, SKEW1, 1, true>, 256);
-  const int slots = P->prob.c2_field ? slots_v : slots_c;
+  const int slots = std::max(1, (P->prob.c2_field ? slots_v : slots_c) / lanes);
   for (int rr = 0; rr < sch.nrounds; ++rr) {
     int n = 0, maxs = 0;
     for (int r = 0; r < P->k; ++r) {
       const int j = P->order[r];
       const int q = rr - sch.round0[j];
-      if (q < 0 || q >= sch.npass[j]) continue;
+      if (lane_of[r] != lane || q < 0 || q >= sch.npass[j]) continue;
       PassSeq<T>& d = pa.seq[n++];
       const double h = P->H / P->steps[j];
       int s0 = 0;
@@ -1516,6 +1517,7 @@ int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX
         d.amp[e] = P->nsrc ? ricker(t0 + (s0 + e) * h, P->f0, P->delay) : 0.0;
       maxs = std::max(maxs, d.strips);
     }
+    if (n == 0) continue;
     pa.max_strips = maxs;
     {
       int strips = 0, gmax = 0;
@@ -1529,9 +1531,9 @@ int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX
     const unsigned blocks = ((unsigned)maxs * pa.nbands + 3) / 4;
     const dim3 grid(blocks, n, P->prob.n_rhs), blk(256);
     if (P->prob.c2_field)
-      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, 1, true>), grid, blk, 0, P->stream, pa);
+      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, 1, true>), grid, blk, 0, stream, pa);
     else
-      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, 1, false>), grid, blk, 0, P->stream, pa);
+      hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, 1, false>), grid, blk, 0, stream, pa);
   }
   for (int j = 0; j < P->k; ++j) {
     const int q = sch.npass[j] - 1;
@@ -1600,78 +1602,95 @@ int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* t
   if (tbar && P->nrec)
     hipLaunchKernelGGL(inject_kernel<T>, dim3((unsigned)((P->nrec + 255) / 256)), dim3(256), 0, s,
                        ybar, P->state, P->rec_dev, P->nrec, tbar, (int)P->rec_distinct);
-  // the forward pairs with the pass shape of the plan's forward form
-  // (its evaluations per pass and time skew; one wavefront per strip)
-  const T* pairs[GBS_MAX_SEQ][2];
-  int st;
-  switch (temporal_shape(resolve_variant(P), 4).G) {
-    case 4: st = forward_pairs<T, 4, false>(P, t0, y0, pairs); break;
-    case 5: st = forward_pairs<T, 5, true>(P, t0, y0, pairs); break;
-    case 6: st = forward_pairs<T, 6, true>(P, t0, y0, pairs); break;
-    default: st = forward_pairs<T, 7, false>(P, t0, y0, pairs); break;
+  // lanes as for the forward passes: folded pairs of sequences, each lane's
+  // forward pairs and backward passes on its own stream
+  const int L = std::max(1, std::min(P->lanes, P->k));
+  int lane_of[GBS_MAX_SEQ];
+  for (int r = 0; r < P->k; ++r) lane_of[r] = std::min(r, P->k - 1 - r) % L;
+  if (L > 1) {
+    hipEventRecord(P->ev_fork, s);
+    for (int l = 1; l < L; ++l) hipStreamWaitEvent(P->lane_stream[l], P->ev_fork, 0);
   }
-  if (st) return st;
-
   PassSchedule sch;
-  st = make_schedule(P->steps, P->k, G, R, 1, sch, false, 0);
+  int st = make_schedule(P->steps, P->k, G, R, 1, sch, false, 0);
   if (st) return st;
-  AdjPassArgs<T> pa;
-  std::memset(&pa, 0, sizeof(pa));
-  T c2c, invz;
-  fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
-  pa.c2c = c2c;
-  pa.src_dev = P->src_dev;
-  pa.zstride = (int64_t)elems;
-  const int nx = (int)P->prob.n[0];
-  static const int slots_c = resident_waves(adj_pass2d<T, G, false>, 256);
-  static const int slots_v = resident_waves(adj_pass2d<T, G, true>, 256);
-  const int slots = P->prob.c2_field ? slots_v : slots_c;
-  for (int rr = 0; rr < sch.nrounds; ++rr) {
-    int n = 0, maxs = 0;
-    for (int r = 0; r < P->k; ++r) {
-      const int j = P->order[r];
-      const int q = rr - sch.round0[j];
-      if (q < 0 || q >= sch.npass[j]) continue;
-      AdjPassSeq<T>& d = pa.seq[n++];
-      const int N = P->steps[j];
-      const double h = P->H / N;
-      // the pass's input level is Z_{s0}: s0 = -1 for the first pass
-      int s0 = -1;
-      for (int qq = 0; qq < q; ++qq) s0 += sch.gsz[j][qq];
-      d.g = sch.gsz[j][q];
-      d.h = (T)h;
-      d.half_cw = (T)(0.5 * P->w[j]);
-      d.flags = (q == 0 ? ADJ_FIRST : 0) | (q == sch.npass[j] - 1 ? ADJ_FINAL : 0);
-      d.cur = q == 0 ? pairs[j][1] : bufs[j].z[(q - 1) % 2][1];
-      d.old = q == 0 ? pairs[j][0] : bufs[j].z[(q - 1) % 2][0];
-      d.ybar = ybar;
-      d.out_a = bufs[j].z[q % 2][0];
-      d.out_b = bufs[j].z[q % 2][1];
-      d.ysum = bufs[j].ysum;
-      d.f1 = bufs[j].f1;
-      d.gsum = bufs[j].gsum;
-      d.strips = (nx + (64 - 2 * d.g * R) - 1) / (64 - 2 * d.g * R);
-      // evaluation e+1 applies f to Y of level e, y_{N - s0 - e - 1}
-      for (int e = 0; e < d.g; ++e)
-        d.amp[e] = P->nsrc ? ricker(t0 + (N - s0 - e - 1) * h, P->f0, P->delay) : 0.0;
-      maxs = std::max(maxs, d.strips);
+  const T* pairs[GBS_MAX_SEQ][2];
+  for (int l = 0; l < L; ++l) {
+    const hipStream_t ls = l == 0 ? s : P->lane_stream[l];
+    // the forward pairs with the pass shape of the plan's forward form
+    // (its evaluations per pass and time skew; one wavefront per strip)
+    switch (temporal_shape(resolve_variant(P), 4).G) {
+      case 4: st = forward_pairs<T, 4, false>(P, t0, y0, pairs, lane_of, l, L, ls); break;
+      case 5: st = forward_pairs<T, 5, true>(P, t0, y0, pairs, lane_of, l, L, ls); break;
+      case 6: st = forward_pairs<T, 6, true>(P, t0, y0, pairs, lane_of, l, L, ls); break;
+      default: st = forward_pairs<T, 7, false>(P, t0, y0, pairs, lane_of, l, L, ls); break;
     }
-    pa.max_strips = maxs;
-    {
-      int strips = 0, gmax = 0;
-      for (int q2 = 0; q2 < n; ++q2) {
-        strips += pa.seq[q2].strips;
-        gmax = std::max(gmax, pa.seq[q2].g);
+    if (st) return st;
+    AdjPassArgs<T> pa;
+    std::memset(&pa, 0, sizeof(pa));
+    T c2c, invz;
+    fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
+    pa.c2c = c2c;
+    pa.src_dev = P->src_dev;
+    pa.zstride = (int64_t)elems;
+    const int nx = (int)P->prob.n[0];
+    static const int slots_c = resident_waves(adj_pass2d<T, G, false>, 256);
+    static const int slots_v = resident_waves(adj_pass2d<T, G, true>, 256);
+    const int slots = std::max(1, (P->prob.c2_field ? slots_v : slots_c) / L);
+    for (int rr = 0; rr < sch.nrounds; ++rr) {
+      int n = 0, maxs = 0;
+      for (int r = 0; r < P->k; ++r) {
+        const int j = P->order[r];
+        const int q = rr - sch.round0[j];
+        if (lane_of[r] != l || q < 0 || q >= sch.npass[j]) continue;
+        AdjPassSeq<T>& d = pa.seq[n++];
+        const int N = P->steps[j];
+        const double h = P->H / N;
+        // the pass's input level is Z_{s0}: s0 = -1 for the first pass
+        int s0 = -1;
+        for (int qq = 0; qq < q; ++qq) s0 += sch.gsz[j][qq];
+        d.g = sch.gsz[j][q];
+        d.h = (T)h;
+        d.half_cw = (T)(0.5 * P->w[j]);
+        d.flags = (q == 0 ? ADJ_FIRST : 0) | (q == sch.npass[j] - 1 ? ADJ_FINAL : 0);
+        d.cur = q == 0 ? pairs[j][1] : bufs[j].z[(q - 1) % 2][1];
+        d.old = q == 0 ? pairs[j][0] : bufs[j].z[(q - 1) % 2][0];
+        d.ybar = ybar;
+        d.out_a = bufs[j].z[q % 2][0];
+        d.out_b = bufs[j].z[q % 2][1];
+        d.ysum = bufs[j].ysum;
+        d.f1 = bufs[j].f1;
+        d.gsum = bufs[j].gsum;
+        d.strips = (nx + (64 - 2 * d.g * R) - 1) / (64 - 2 * d.g * R);
+        // evaluation e+1 applies f to Y of level e, y_{N - s0 - e - 1}
+        for (int e = 0; e < d.g; ++e)
+          d.amp[e] = P->nsrc ? ricker(t0 + (N - s0 - e - 1) * h, P->f0, P->delay) : 0.0;
+        maxs = std::max(maxs, d.strips);
       }
-      pa.band = band_for_round(P, strips, gmax, R, R, slots);
-      pa.nbands = (int)((P->prob.n[1] + pa.band - 1) / pa.band);
+      if (n == 0) continue;
+      pa.max_strips = maxs;
+      {
+        int strips = 0, gmax = 0;
+        for (int q2 = 0; q2 < n; ++q2) {
+          strips += pa.seq[q2].strips;
+          gmax = std::max(gmax, pa.seq[q2].g);
+        }
+        pa.band = band_for_round(P, strips, gmax, R, R, slots);
+        pa.nbands = (int)((P->prob.n[1] + pa.band - 1) / pa.band);
+      }
+      const unsigned blocks = ((unsigned)maxs * pa.nbands + 3) / 4;
+      const dim3 grid(blocks, n, P->prob.n_rhs), blk(256);
+      if (P->prob.c2_field)
+        hipLaunchKernelGGL((adj_pass2d<T, G, true>), grid, blk, 0, ls, pa);
+      else
+        hipLaunchKernelGGL((adj_pass2d<T, G, false>), grid, blk, 0, ls, pa);
     }
-    const unsigned blocks = ((unsigned)maxs * pa.nbands + 3) / 4;
-    const dim3 grid(blocks, n, P->prob.n_rhs), blk(256);
-    if (P->prob.c2_field)
-      hipLaunchKernelGGL((adj_pass2d<T, G, true>), grid, blk, 0, s, pa);
-    else
-      hipLaunchKernelGGL((adj_pass2d<T, G, false>), grid, blk, 0, s, pa);
+  }  // lanes
+  if (L > 1) {
+    for (int l = 1; l < L; ++l) {
+      hipEventRecord(P->ev_join[l], P->lane_stream[l]);
+      hipStreamWaitEvent(s, P->ev_join[l], 0);
+    }
   }
   AdjSumArgs<T> sa;
   std::memset(&sa, 0, sizeof(sa));

@@ -216,3 +216,25 @@ def test_blocked_adjoint_matches_streaming(dtype, tol, band):
         res.append((ybar.double().cpu().numpy(), grad.cpu().numpy()))
     assert rel_err(res[1][0], res[0][0]) <= tol
     assert rel_err(res[1][1], res[0][1]) <= tol
+
+
+def test_blocked_adjoint_lanes_do_not_change_the_result():
+    ny, nx = 150, 130
+    cs = fields.lognormal_speed((ny, nx), seed=18)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(nx, ny), 2,
+                           workloads.SIGMA_FD4)
+    rng = np.random.default_rng(19)
+    y0 = to_dev(rng.standard_normal((1, 3, ny, nx)))
+    wbar = rng.standard_normal((1, 3, ny, nx))
+    s = fields.ricker_source_2d(max(nx, ny), cells_per_wavelength=6.0)
+    res = []
+    for lanes in (1, 3):
+        plan = lib_plan(B.ACOUSTIC2D, (nx, ny), schemes.ORDER8_K6, H, c2_field=to_dev(cs ** 2),
+                        c_max=float(cs.max()))
+        plan.set_sources([0], [70 * nx + 40], [s["weight"] * 1e-3], s["f0"], s["delay"])
+        plan.set_lanes(lanes)
+        ybar = to_dev(wbar)
+        grad = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+        plan.adjoint_step(0.9 * s["delay"], y0, ybar, grad_c2=grad)
+        res.append((ybar.clone(), grad.clone()))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
