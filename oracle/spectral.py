@@ -70,6 +70,29 @@ def advection1d(u0, H, steps, c, n_macro, r=2):
 
 def acoustic(y0, c2, H, steps, c, n_macro, r=2):
     """Constant-c acoustic system, y0 of shape (1+d, *grid)."""
+    return _acoustic_g(y0, c2, lambda iw: amplification(iw, H, steps, c, n_macro), r)
+
+
+def rk4_amplification(lam, h, n_steps):
+    """(1 + z + z^2/2 + z^3/6 + z^4/24)^n, z = h lambda, longdouble."""
+    z = np.longdouble(float(h)) * np.asarray(lam).astype(np.clongdouble)
+    one = np.longdouble(1)
+    r = one + z * (one + z * (one / 2 + z * (one / 6 + z / 24)))
+    return r ** n_steps
+
+
+def acoustic_rk4(y0, c2, h, n_steps, r=2):
+    """n_steps classical RK4 steps of size h, constant-c acoustic system."""
+    return _acoustic_g(y0, c2, lambda iw: rk4_amplification(iw, h, n_steps), r)
+
+
+def acoustic_exact(y0, c2, t, r=2):
+    """The semi-discrete solution exp(t A) y0 (constant c)."""
+    return _acoustic_g(y0, c2, lambda iw: np.exp(np.longdouble(float(t)) * iw), r)
+
+
+def _acoustic_g(y0, c2, g_of, r):
+    """g(A) y0 for g(0) = 1 real on the real axis, given g at i w."""
     y0 = np.asarray(y0, dtype=np.float64)
     grid = y0.shape[1:]
     d = len(grid)
@@ -85,7 +108,7 @@ def acoustic(y0, c2, H, steps, c, n_macro, r=2):
         svec.append(np.broadcast_to(s.reshape(shape), grid))
     s2 = sum(sk * sk for sk in svec)
     w = np.sqrt(c2 * s2)
-    g = amplification(1j * w, H, steps, c, n_macro)            # R(i w)^n
+    g = g_of(1j * w.astype(np.longdouble))                     # g(i w)
     wl = w.astype(np.longdouble)
     safe = np.where(wl > 0, wl, np.longdouble(1))
     beta = np.where(wl > 0, g.imag / safe, 0).astype(np.float64)
