@@ -175,6 +175,19 @@ int gbs_plan_set_sources(gbs_plan* plan, int32_t n_src, const int32_t* rhs,
 int gbs_step(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in, void* y_out);
 
 /*
+ * gbs_rk4_step — n_steps classical fourth-order Runge-Kutta steps of size h
+ * from t0 (step i starts at t0 + i*h) with the plan's operator, coefficient,
+ * sources and dtype: the comparison method of Sect. 3.8 and App. A, on the
+ * same stencil code (one streaming launch per stage; the stage sum
+ * k1 + 2 k2 + 2 k3 + k4 in FP64).  y_in / y_out as for gbs_step (may alias).
+ * Unless GBS_FLAG_NO_STABILITY_CHECK is set, h * rho must not exceed RK4's
+ * imaginary stability boundary 2 sqrt 2 -> GBS_EUNSTABLE.  Uses the plan's
+ * workspace (calls on one plan must not overlap).
+ */
+int gbs_rk4_step(gbs_plan* plan, double t0, int32_t n_steps, double h, const void* y_in,
+                 void* y_out);
+
+/*
  * gbs_plan_set_variant — choose the leap-frog kernel (all variants compute
  * the same values in the same order; they differ in work layout only):
  *   GBS_VARIANT_AUTO        library's choice (default): 2-D acoustic

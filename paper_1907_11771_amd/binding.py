@@ -74,6 +74,7 @@ def lib():
             "gbs_plan_create": [P(vp), P(Problem), P(Scheme), dbl, vp, sz, vp],
             "gbs_plan_set_sources": [vp, i32, P(i32), P(i64), P(dbl), dbl, dbl],
             "gbs_step": [vp, dbl, i32, vp, vp],
+            "gbs_rk4_step": [vp, dbl, i32, dbl, vp, vp],
             "gbs_plan_set_timing": [vp, i32],
             "gbs_plan_set_variant": [vp, i32],
             "gbs_plan_get_variant": [vp, P(i32)],

@@ -387,4 +387,56 @@ __global__ __launch_bounds__(256) void first_kernel(const FirstArgs<T> a) {
   }
 }
 
+// Classical RK4 on the same operators (the comparison method of Sect. 3.8
+// and App. A), one launch per stage, every point independent:
+//   stage 0: K = k1,       next = y + h/2 k1
+//   stage 1: K += 2 k2,    next = y + h/2 k2
+//   stage 2: K += 2 k3,    next = y + h k3
+//   stage 3: y_new = y + h/6 (K + k4)
+// with k_s = f(t_s, stage input).  K is kept in FP64 (FP32 stepping keeps
+// the stage inputs in FP32, as the extrapolated step keeps its levels).
+template <typename T>
+struct RK4Args {
+  Geometry g;
+  SrcDesc src[GBS_MAX_SRC];
+  const T* c2f;
+  T c2c, invx, invy, invz;
+  const T* yn;       // the state at the step's start
+  const T* ys;       // this stage's input
+  T* out;            // next stage's input, or the new state (stage 3)
+  double* acc;       // K (FP64, state-sized)
+  double h;
+  double amp;        // source wavelet at this stage's time
+  int32_t stage;
+};
+
+template <typename T, int ORDER, int OP>
+__global__ __launch_bounds__(256) void rk4_stage(const RK4Args<T> a) {
+  constexpr int F = NFields<OP>::F;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.g.field) return;
+  const int64_t rhs = blockIdx.z;
+  const int64_t base = rhs * a.g.state;
+  int x, y, z;
+  decompose(idx, a.g, x, y, z);
+  const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
+  T f[F];
+  eval_rhs<T, ORDER, OP>(a.ys + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
+  if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
+#pragma unroll
+  for (int q = 0; q < F; ++q) {
+    const int64_t e = base + q * a.g.field + idx;
+    const double k = (double)f[q];
+    if (a.stage == 0) {
+      a.acc[e] = k;
+      a.out[e] = a.yn[e] + (T)(0.5 * a.h) * f[q];
+    } else if (a.stage < 3) {
+      a.acc[e] = a.acc[e] + 2.0 * k;
+      a.out[e] = a.yn[e] + (T)(a.stage == 1 ? 0.5 * a.h : a.h) * f[q];
+    } else {
+      a.out[e] = (T)((double)a.yn[e] + (a.h / 6.0) * (a.acc[e] + k));
+    }
+  }
+}
+
 }  // namespace gbs

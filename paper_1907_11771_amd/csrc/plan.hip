@@ -220,6 +220,17 @@ int check_stable(const gbs_problem* prob, const gbs_scheme* sch, double H) {
   return GBS_OK;
 }
 
+// rho = c_max sigma sqrt(sum_a n_a^2): the operator's spectral radius bound
+double rho_of(const gbs_problem* prob) {
+  const int d = dims_of(prob->op);
+  double s2 = 0;
+  for (int a = 0; a < d; ++a) s2 += (double)prob->n[a] * (double)prob->n[a];
+  const double cmax = prob->op == GBS_ADVECT1D
+                          ? 1.0
+                          : (prob->c2_field ? prob->c_max : std::sqrt(prob->c2));
+  return cmax * stencil_sigma(prob->fd_order) * std::sqrt(s2);
+}
+
 double ricker(double t, double f0, double delay) {
   const double pi = 3.14159265358979323846;
   const double a = (pi * f0 * (t - delay)) * (pi * f0 * (t - delay));
@@ -614,6 +625,49 @@ int run(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   return GBS_OK;
 }
 
+template <typename T, int ORDER, int OP>
+int run_rk4(gbs_plan* P, double t0, int n_steps, double h, const T* yin, T* yout) {
+  RK4Args<T> ra;
+  std::memset(&ra, 0, sizeof(ra));
+  fill_geometry<T>(P, ra.g, ra.c2c, ra.c2f, ra.invx, ra.invy, ra.invz);
+  std::memcpy(ra.src, P->src, sizeof(P->src));
+  ra.acc = P->acc;
+  ra.h = h;
+  T* st[2] = {(T*)P->lev[0][0], (T*)P->lev[0][1]};
+  const unsigned gx = (unsigned)((P->field + 255) / 256);
+  const unsigned gz = (unsigned)P->prob.n_rhs;
+  const double frac[4] = {0.0, 0.5, 0.5, 1.0};
+  for (int m = 0; m < n_steps; ++m) {
+    const double t = t0 + m * h;
+    ra.yn = m == 0 ? yin : yout;
+    for (int s = 0; s < 4; ++s) {
+      ra.stage = s;
+      ra.ys = s == 0 ? ra.yn : st[(s - 1) % 2];
+      ra.out = s == 3 ? yout : st[s % 2];
+      ra.amp = P->nsrc ? ricker(t + frac[s] * h, P->f0, P->delay) : 0.0;
+      hipLaunchKernelGGL((rk4_stage<T, ORDER, OP>), dim3(gx, 1, gz), dim3(256), 0, P->stream, ra);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GBS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return GBS_OK;
+}
+
+template <typename T>
+int dispatch_rk4(gbs_plan* P, double t0, int n, double h, const void* yin, void* yout) {
+  const T* a = (const T*)yin;
+  T* b = (T*)yout;
+  const int op = P->prob.op;
+  if (P->prob.fd_order == 4) {
+    if (op == GBS_ADVECT1D) return run_rk4<T, 4, OP_ADV1D>(P, t0, n, h, a, b);
+    if (op == GBS_ACOUSTIC2D) return run_rk4<T, 4, OP_AC2D>(P, t0, n, h, a, b);
+    return run_rk4<T, 4, OP_AC3D>(P, t0, n, h, a, b);
+  }
+  if (op == GBS_ADVECT1D) return run_rk4<T, 8, OP_ADV1D>(P, t0, n, h, a, b);
+  if (op == GBS_ACOUSTIC2D) return run_rk4<T, 8, OP_AC2D>(P, t0, n, h, a, b);
+  return run_rk4<T, 8, OP_AC3D>(P, t0, n, h, a, b);
+}
+
 template <typename T>
 int dispatch_order(gbs_plan* P, double t0, int n, const void* yin, void* yout) {
   const T* a = (const T*)yin;
@@ -757,6 +811,29 @@ extern "C" int gbs_step(gbs_plan* P, double t0, int32_t n_macro, const void* y_i
   }
   if (P->prob.dtype == GBS_F64) return dispatch_order<double>(P, t0, n_macro, y_in, y_out);
   return dispatch_order<float>(P, t0, n_macro, y_in, y_out);
+}
+
+extern "C" int gbs_rk4_step(gbs_plan* P, double t0, int32_t n_steps, double h, const void* y_in,
+                            void* y_out) {
+  if (!P || !y_in || !y_out) return fail(GBS_EINVAL, "null argument");
+  if (n_steps < 0) return fail(GBS_EINVAL, "n_steps must be >= 0");
+  if (!std::isfinite(t0) || !(h > 0) || !std::isfinite(h))
+    return fail(GBS_EINVAL, "t0 must be finite and h positive");
+  if (!(P->prob.flags & GBS_FLAG_NO_STABILITY_CHECK)) {
+    const double isb = 2.0 * std::sqrt(2.0);           // App. A: RK4's imaginary boundary
+    const double hr = h * rho_of(&P->prob);
+    if (hr > isb) return fail(GBS_EUNSTABLE, "h * rho = %.6g exceeds RK4's ISB 2 sqrt 2", hr);
+  }
+  if (n_steps == 0) {
+    if (y_in != y_out) {
+      const size_t bytes = (size_t)P->prob.n_rhs * P->state * dsize(P->prob.dtype);
+      if (hipMemcpyAsync(y_out, y_in, bytes, hipMemcpyDeviceToDevice, P->stream) != hipSuccess)
+        return fail(GBS_EDEVICE, "copy failed");
+    }
+    return GBS_OK;
+  }
+  if (P->prob.dtype == GBS_F64) return dispatch_rk4<double>(P, t0, n_steps, h, y_in, y_out);
+  return dispatch_rk4<float>(P, t0, n_steps, h, y_in, y_out);
 }
 
 extern "C" int gbs_plan_set_variant(gbs_plan* P, int32_t variant) {

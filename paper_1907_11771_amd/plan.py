@@ -77,6 +77,18 @@ class GBSPlan:
                                  out.data_ptr()))
         return out
 
+    def rk4_step(self, y, out=None, t0=0.0, n_steps=1, h=None):
+        """n_steps classical RK4 steps of size h (default: the plan's H) with
+        the plan's operator; returns the output tensor."""
+        self._check_state(y)
+        if out is None:
+            out = torch.empty_like(y)
+        self._check_state(out)
+        B.check(B.lib().gbs_rk4_step(self.handle, float(t0), int(n_steps),
+                                     float(self.H if h is None else h), y.data_ptr(),
+                                     out.data_ptr()))
+        return out
+
     def set_sources(self, rhs, flat_index, weight, f0, delay):
         n = len(rhs)
         B.check(B.lib().gbs_plan_set_sources(self.handle, n, B._arr(ctypes.c_int32, rhs),
