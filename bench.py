@@ -365,6 +365,70 @@ def bench_3d(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_rk4(args):
+    """Time to solution at equal error, the extrapolated step against
+    classical RK4 on the same stencil code (Sect. 3.8, App. A): 2048^2
+    constant-c acoustic, FP64, a pulse plus 32 modes up to wavenumber 64; the
+    extrapolated step at 0.8 of its stability limit for 100 macro steps (the
+    library's autotuned blocked form), RK4 with the fewest steps found whose
+    error is no larger.  Errors are taken against the same scheme at H/4
+    (order 8: its own error is 4^8 times smaller), all on the GPU."""
+    import math
+    import torch
+    from paper_1907_11771_amd import binding as B
+    from paper_1907_11771_amd.plan import GBSPlan, scheme_weights
+    from synth import fields, workloads
+
+    cfg = workloads.CONFIG_ACOUSTIC2D
+    n, H = cfg["n"], cfg["H"]
+    nm = 100 if args.steps == 500 else args.steps
+    steps, w, _ = scheme_weights(cfg["scheme"])
+    dev = torch.device("cuda:0")
+    y = torch.from_numpy(fields.acoustic2d_pulse_modes(n, n_modes=32, kmax=64, seed=0)[None])
+    y = y.to(dev)
+    T = nm * H
+    plan = GBSPlan(B.ACOUSTIC2D, (n, n), 8, steps, w, H, dtype=torch.float64, device=dev)
+    fine = GBSPlan(B.ACOUSTIC2D, (n, n), 8, steps, w, H / 4, dtype=torch.float64, device=dev)
+    ref = fine.step(y, n_macro=4 * nm)
+    scale = float(ref.abs().max())
+    err = lambda a: float((a - ref).abs().max()) / scale
+    out = torch.empty_like(y)
+    tuned = plan.autotune(y, out, macro_steps=3, lanes=1)
+
+    def timed(fn):
+        fn()                                          # warm-up run of the same length
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    t_gbs, yg = timed(lambda: plan.step(y, out, n_macro=nm))
+    e_gbs = err(yg)
+    # RK4 from 0.8 of its own limit h rho <= 2 sqrt 2, refined (error ~ h^4)
+    # until its error is within the extrapolated step's
+    rho = math.sqrt(cfg["c2"]) * workloads.SIGMA_FD4 * n * math.sqrt(2)
+    m = math.ceil(T / (0.8 * 2 * math.sqrt(2) / rho))
+    out2 = torch.empty_like(y)
+    e_rk, tries = err(plan.rk4_step(y, out2, n_steps=m, h=T / m)), 0
+    while e_rk > e_gbs and tries < 8:
+        m = math.ceil(m * max(1.03, 1.01 * (e_rk / e_gbs) ** 0.25))
+        e_rk, tries = err(plan.rk4_step(y, out2, n_steps=m, h=T / m)), tries + 1
+    t_rk, _ = timed(lambda: plan.rk4_step(y, out2, n_steps=m, h=T / m))
+    print(json.dumps(dict(
+        metric="time to solution at equal error vs RK4", value=t_gbs, unit="s",
+        higher_is_better=False, n_gpus=1, steps=nm, dtype="f64", data="synthetic",
+        config=dict(workload="gbs_vs_rk4_acoustic2d_2048", grid=[n, n], t_end=T,
+                    initial="pulse + 32 modes, wavenumbers up to 64",
+                    error="max |y - y_ref| / max |y_ref|, y_ref: same scheme at H/4",
+                    autotuned=dict(variant=tuned[0], band=tuned[1], lanes=tuned[2])),
+        gbs=dict(seconds=t_gbs, macro_steps=nm, rhs_evaluations=nm * (1 + sum(steps)),
+                 rel_error=e_gbs),
+        rk4=dict(seconds=t_rk, steps=m, rhs_evaluations=4 * m, rel_error=e_rk,
+                 reached_equal_error=e_rk <= e_gbs),
+        speedup=t_rk / t_gbs)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,7 +440,7 @@ def main():
     ap.add_argument("--band", type=int, default=0,
                     help="rows per band of the temporally blocked passes (0 = default)")
     ap.add_argument("--workload", default="acoustic2d",
-                    choices=["acoustic2d", "batch64", "adjoint1024", "acoustic3d"],
+                    choices=["acoustic2d", "batch64", "adjoint1024", "acoustic3d", "rk4"],
                     help="acoustic2d: the 2048^2 FP64 workload (default); batch64: 64 "
                          "uneven instances in one batch; adjoint1024: forward + adjoint "
                          "gradient of the 1024^2 receiver misfit; acoustic3d: 384^3 FD8, "
@@ -415,6 +479,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "acoustic3d":
         return bench_3d(args)
+    if args.workload == "rk4":
+        return bench_rk4(args)
 
     cfg = workloads.CONFIG_ACOUSTIC2D
     n = cfg["n"]

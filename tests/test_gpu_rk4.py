@@ -74,3 +74,25 @@ def test_rk4_fp32_stepping_error_and_stability_check():
     with pytest.raises(B.GBSError) as ei:
         p64.rk4_step(to_dev(y0[None]), n_steps=1, h=1.01 * h / 0.8)
     assert ei.value.status == B.GBS_EUNSTABLE
+
+
+def test_fine_run_reference_of_the_time_to_solution_comparison():
+    # the comparison measures errors against the same scheme at H/4; here
+    # that estimate is checked against the semi-discrete solution exp(tA) y0
+    from oracle import spectral as SP
+    from paper_1907_11771_amd.plan import scheme_weights
+    n, nm = 128, 20
+    steps, w, isb = scheme_weights(schemes.ORDER8_K6)
+    H = workloads.stable_H(isb, 1.0, 1.0 / n, 2, workloads.SIGMA_FD4)
+    y0 = fields.acoustic2d_pulse_modes(n, n_modes=8, kmax=6, width=0.1, seed=5)
+    exact = SP.acoustic_exact(y0, 1.0, nm * H)
+    coarse = lib_plan(B.ACOUSTIC2D, (n, n), schemes.ORDER8_K6, H)
+    fine = lib_plan(B.ACOUSTIC2D, (n, n), schemes.ORDER8_K6, H / 4)
+    yc = coarse.step(to_dev(y0[None]), n_macro=nm).cpu().numpy()[0]
+    yf = fine.step(to_dev(y0[None]), n_macro=4 * nm).cpu().numpy()[0]
+    e_true = np.max(np.abs(yc - exact))
+    e_fine = np.max(np.abs(yf - exact))
+    e_est = np.max(np.abs(yc - yf))
+    print("coarse", e_true, "fine", e_fine, "estimate", e_est)
+    assert e_fine <= e_true / 1000
+    assert abs(e_est - e_true) <= 0.01 * e_true

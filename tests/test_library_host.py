@@ -242,3 +242,28 @@ def test_lanes_validation_on_host():
         B.check(B.lib().gbs_plan_set_lanes(h, 1))
     finally:
         B.plan_destroy(h)
+
+
+def test_rk4_entry_validates_on_host():
+    # every check of gbs_rk4_step runs before any device call: RK4's
+    # imaginary stability boundary 2 sqrt 2 (App. A) against h rho
+    steps, w = _cfg2()
+    n = 64
+    pr = B.make_problem(B.ACOUSTIC2D, (n, n))
+    sc = B.make_scheme(8, steps, w)
+    h = B.plan_create(pr, sc, 1e-4, FAKE_WS, B.workspace_bytes(pr, sc))
+    rho = 1.3722220 * (2 * n * n) ** 0.5
+    lim = 2 * 2 ** 0.5 / rho
+    ptr = ctypes.c_void_p(FAKE_WS)
+    try:
+        L = B.lib()
+        assert L.gbs_rk4_step(h, 0.0, 1, 1.001 * lim, ptr, ptr) == B.GBS_EUNSTABLE
+        assert L.gbs_rk4_step(h, 0.0, -1, 0.5 * lim, ptr, ptr) == B.GBS_EINVAL
+        assert L.gbs_rk4_step(h, 0.0, 1, 0.0, ptr, ptr) == B.GBS_EINVAL
+        assert L.gbs_rk4_step(h, float("nan"), 1, 0.5 * lim, ptr, ptr) == B.GBS_EINVAL
+        assert L.gbs_rk4_step(h, 0.0, 1, 0.5 * lim, None, ptr) == B.GBS_EINVAL
+        assert L.gbs_rk4_step(None, 0.0, 1, 0.5 * lim, ptr, ptr) == B.GBS_EINVAL
+        # n_steps = 0 in place is a no-op that touches nothing
+        assert L.gbs_rk4_step(h, 0.0, 0, 0.5 * lim, ptr, ptr) == B.GBS_OK
+    finally:
+        B.plan_destroy(h)
