@@ -115,3 +115,29 @@ class Acoustic:
             out[0] += d1(w[1 + k], axis=ax, dx=self.dx[ax], r=self.r)
             out[1 + k] = d1(cw, axis=ax, dx=self.dx[ax], r=self.r)
         return out
+
+
+class SpectralAdvection1D:
+    """u_t = -u_x with the Fourier (spectral) first derivative on M points of
+    [0,1), the spatial operator of the paper's experiment (Sect. 4.1): the
+    derivative of the trigonometric interpolant, i.e. multiplication of DFT
+    mode k by 2 pi i k, |k| < M/2; for even M the mode k = M/2 is set to zero
+    (its interpolant cos(pi M x) has zero derivative at every grid point).
+    State shape (1, M)."""
+
+    def __init__(self, m):
+        self.m = m
+        k = np.fft.fftfreq(m, 1.0 / m)
+        if m % 2 == 0:
+            k[m // 2] = 0.0
+        self.ik = 2j * np.pi * k
+
+    def derivative(self, u):
+        return np.real(np.fft.ifft(self.ik * np.fft.fft(u, axis=-1), axis=-1))
+
+    def __call__(self, t, y):
+        return -self.derivative(y)
+
+    def matvec_T(self, w):
+        """A^T w: the derivative is skew-symmetric."""
+        return self.derivative(w)
