@@ -365,6 +365,64 @@ def bench_3d(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_oneway(args):
+    """The paper's experiment (Sect. 4.1) on the GPU: u_t + u_x = 0 on [0,1)
+    with the Fourier derivative, u(x,0) = (1 - cos 2 pi x)/2, one revolution
+    at 0.99 of each method's limit (n = ceil(pi M / (0.99 ISB)) steps of
+    1/n), refined over M; the error is max |u_n - u(., 1)| against the
+    analytic solution u(x, 1) = u(x, 0).  Methods: GBS_{8,6}, GBS_{12,8}
+    (FP64 weights from the exact rationals) and RK4; the normalised step is
+    H over the evaluations per step per core (N_max + 1 for the folded
+    sequences, 4 for RK4)."""
+    import math
+    import torch
+    from paper_1907_11771_amd import binding as B
+    from paper_1907_11771_amd.plan import GBSPlan, scheme_weights
+    from synth import fields, schemes
+
+    dev = torch.device("cuda:0")
+    ms = (16, 32, 64, 128, 256, 512, 1024)
+    rows = []
+    t_all = time.perf_counter()
+    for sch in (schemes.GBS_8_6, schemes.GBS_12_8, None):
+        if sch is None:
+            name, isb, per_core, evals = "rk4", 2 * math.sqrt(2), 4, 4
+            steps, w, p = [2, 4, 6, 8], None, 8
+        else:
+            steps, w, isb = scheme_weights(sch)
+            name, p = sch["name"], sch["p"]
+            per_core, evals = max(steps) + 1, 1 + sum(steps)
+        for m in ms:
+            n = math.ceil(math.pi * m / (0.99 * isb))
+            u0 = torch.from_numpy(fields.oneway_initial(m)[None]).to(dev)
+            if sch is None:
+                plan = GBSPlan(B.ADVECT1D, (m,), 8, *scheme_weights(schemes.ORDER8_K6)[:2],
+                               1e-9, fd_order=B.FD_SPECTRAL, device=dev)
+                go = lambda: plan.rk4_step(u0, n_steps=n, h=1.0 / n)
+            else:
+                plan = GBSPlan(B.ADVECT1D, (m,), p, steps, w, 1.0 / n,
+                               fd_order=B.FD_SPECTRAL, device=dev)
+                go = lambda: plan.step(u0, n_macro=n)
+            go()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            u = go()
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t
+            err = float((u - u0).abs().max())
+            rows.append(dict(method=name, M=m, steps=n, H=1.0 / n,
+                             normalised_step=1.0 / n / per_core, evaluations=n * evals,
+                             error=err, seconds=t))
+            print("oneway", name, m, n, err, t, flush=True)
+    best = min(r["error"] for r in rows if r["method"] == "gbs_8_6")
+    print(json.dumps(dict(
+        metric="one-way wave, one revolution: lowest error of GBS_{8,6}", value=best,
+        unit="max abs error", higher_is_better=False, n_gpus=1, dtype="f64", data="synthetic",
+        config=dict(workload="oneway_spectral_sect4_1", M=list(ms), lam="0.99 ISB / pi",
+                    seconds_total=time.perf_counter() - t_all),
+        rows=rows)), flush=True)
+
+
 def bench_rk4(args):
     """Time to solution at equal error, the extrapolated step against
     classical RK4 on the same stencil code (Sect. 3.8, App. A): 2048^2
@@ -440,7 +498,8 @@ def main():
     ap.add_argument("--band", type=int, default=0,
                     help="rows per band of the temporally blocked passes (0 = default)")
     ap.add_argument("--workload", default="acoustic2d",
-                    choices=["acoustic2d", "batch64", "adjoint1024", "acoustic3d", "rk4"],
+                    choices=["acoustic2d", "batch64", "adjoint1024", "acoustic3d", "rk4",
+                             "oneway"],
                     help="acoustic2d: the 2048^2 FP64 workload (default); batch64: 64 "
                          "uneven instances in one batch; adjoint1024: forward + adjoint "
                          "gradient of the 1024^2 receiver misfit; acoustic3d: 384^3 FD8, "
@@ -481,6 +540,8 @@ def main():
         return bench_3d(args)
     if args.workload == "rk4":
         return bench_rk4(args)
+    if args.workload == "oneway":
+        return bench_oneway(args)
 
     cfg = workloads.CONFIG_ACOUSTIC2D
     n = cfg["n"]

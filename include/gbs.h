@@ -33,7 +33,13 @@
  *   GBS_ACOUSTIC2D  F = 3 (p, v_x, v_y),                grid Y x X
  *   GBS_ACOUSTIC3D  F = 4 (p, v_x, v_y, v_z),           grid Z x Y x X
  * on the periodic unit box with spacing 1/n per axis.  The operators are the
- * periodic centred first-derivative stencils of order 4 or 8:
+ * periodic centred first-derivative stencils of order 4 or 8, or, for
+ * GBS_ADVECT1D only, the Fourier (spectral) derivative of the paper's own
+ * experiment (Sect. 4.1; fd_order = GBS_FD_SPECTRAL): the derivative of the
+ * trigonometric interpolant on the n points, mode k multiplied by 2 pi i k
+ * for |k| < n/2 and the mode n/2 of an even n by 0, applied on the device as
+ * the equivalent centred sum over all n points (n^2 work per evaluation,
+ * 4 <= n <= 8192):
  *   advection  u_t = -u_x
  *   acoustic   p_t = -c^2 div v + sum_s w_s r(t) delta_s,   v_t = -grad p
  * with r the Ricker wavelet of the plan's sources (if any).
@@ -61,13 +67,15 @@ enum {
 };
 
 enum { GBS_ADVECT1D = 1, GBS_ACOUSTIC2D = 2, GBS_ACOUSTIC3D = 3 };
+/* fd_order value of the Fourier derivative (GBS_ADVECT1D only) */
+enum { GBS_FD_SPECTRAL = 0 };
 enum { GBS_F32 = 1, GBS_F64 = 2 };
 /* plan flags */
 enum { GBS_FLAG_NO_STABILITY_CHECK = 1 };
 
 typedef struct gbs_problem {
   int32_t op;           /* GBS_ADVECT1D / GBS_ACOUSTIC2D / GBS_ACOUSTIC3D            */
-  int32_t fd_order;     /* 4 or 8                                                    */
+  int32_t fd_order;     /* 4 or 8, or GBS_FD_SPECTRAL with GBS_ADVECT1D              */
   int64_t n[3];         /* points along x, y, z (unused axes: 1)                     */
   int32_t n_rhs;        /* R >= 1 independent states sharing the coefficient field   */
   int32_t dtype;        /* GBS_F64, or GBS_F32 (stepping in FP32; the averaging and  */

@@ -77,6 +77,17 @@ def error_closed_form(m, poly, n, dps=60):
         return float(err)
 
 
+def solution_closed_form(m, poly, n, dps=60):
+    """u_n at the M grid points (extended precision, rounded to FP64 at the
+    end) for a method with stability polynomial ``poly`` and n steps."""
+    with mp.workdps(dps):
+        coef = [mp.mpf(Fraction(a).numerator) / Fraction(a).denominator for a in poly]
+        r0 = S.poly_eval(coef, mp.mpf(0)) ** n
+        g = S.poly_eval(coef, -2j * mp.pi / n) ** n
+        return np.array([[float(r0 / 2 - mp.re(g * mp.expjpi(2 * mp.mpf(i) / m)) / 2)
+                          for i in range(m)]])
+
+
 def gbs_poly(steps, c):
     """R(xi) = sum_j c_j P_{N_j}(xi) with the weights taken exactly as given
     (Fractions, or floats at their binary values)."""

@@ -14,6 +14,7 @@ from . import build as _build
 GBS_OK, GBS_EINVAL, GBS_ESTEPS, GBS_EORDER = 0, -1, -2, -3
 GBS_ESINGULAR, GBS_EUNSTABLE, GBS_EDEVICE, GBS_ENOMEM, GBS_EUNSUPPORTED = -4, -5, -6, -7, -8
 ADVECT1D, ACOUSTIC2D, ACOUSTIC3D = 1, 2, 3
+FD_SPECTRAL = 0                 # fd_order of the Fourier derivative (ADVECT1D)
 F32, F64 = 1, 2
 FLAG_NO_STABILITY_CHECK = 1
 VARIANT_AUTO, VARIANT_FLAT, VARIANT_MARCH8, VARIANT_MARCH16 = 0, 1, 2, 3

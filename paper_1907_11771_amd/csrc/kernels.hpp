@@ -27,13 +27,16 @@ template <> struct NFields<OP_AC3D> { static constexpr int F = 4; };
 
 // f(t, y) at grid point (x, y, z) of one right-hand side (without sources).
 // Fields (p, v_x, v_y[, v_z]):  f_p = -c^2 div v,  f_v = -grad p;
-// advection: f_u = -u_x.
+// advection: f_u = -u_x (ORDER = GBS_FD_SPECTRAL: the Fourier derivative).
 template <typename T, int ORDER, int OP>
 __device__ __forceinline__ void eval_rhs(const T* __restrict__ s, int x, int y, int z,
                                          const Geometry& g, T c2, T invx, T invy, T invz,
                                          T* f) {
   if constexpr (OP == OP_ADV1D) {
-    f[0] = -(invx * dsum<T, ORDER>(s, x, g.nx, 1));
+    if constexpr (ORDER == GBS_FD_SPECTRAL)
+      f[0] = -fourier_dsum<T>(s, x, g.nx, (const T*)g.fourier);
+    else
+      f[0] = -(invx * dsum<T, ORDER>(s, x, g.nx, 1));
   } else if constexpr (OP == OP_AC2D) {
     const int64_t row = (int64_t)y * g.nx;
     const T* p = s;

@@ -75,6 +75,11 @@ struct gbs_plan {
   bool rec_distinct = true;   // no two receivers share a (rhs, point)
   RecDesc* rec_dev = nullptr;
   double f0 = 0, delay = 0;
+  // Fourier-derivative weights (spectral advection): host copy in the
+  // state's type, device copy in the workspace, uploaded before the first step
+  std::vector<unsigned char> fourier_host;
+  void* fourier_dev = nullptr;
+  bool fourier_ready = false;
   // leap-frog kernel variant (GBS_VARIANT_*) and rows per band of the
   // temporally blocked passes
   int variant = 0;
@@ -97,6 +102,7 @@ struct gbs_plan {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kFourierMax = 8192;   // the Fourier derivative costs n^2 per evaluation
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int fields_of(int op) {
@@ -108,7 +114,14 @@ size_t dsize(int dtype) { return dtype == GBS_F32 ? 4 : 8; }
 int validate_problem(const gbs_problem* p) {
   if (!p) return fail(GBS_EINVAL, "problem is null");
   if (!fields_of(p->op)) return fail(GBS_EINVAL, "unknown operator %d", p->op);
-  if (p->fd_order != 4 && p->fd_order != 8) return fail(GBS_EUNSUPPORTED, "fd_order must be 4 or 8");
+  if (p->fd_order == GBS_FD_SPECTRAL) {
+    if (p->op != GBS_ADVECT1D)
+      return fail(GBS_EUNSUPPORTED, "the Fourier derivative is built for GBS_ADVECT1D only");
+    if (p->n[0] < 4 || p->n[0] > kFourierMax)
+      return fail(GBS_EINVAL, "the Fourier derivative needs 4 <= n <= %d points", kFourierMax);
+  } else if (p->fd_order != 4 && p->fd_order != 8) {
+    return fail(GBS_EUNSUPPORTED, "fd_order must be 4, 8 or GBS_FD_SPECTRAL");
+  }
   if (p->dtype != GBS_F32 && p->dtype != GBS_F64) return fail(GBS_EINVAL, "dtype must be F32 or F64");
   if (p->n_rhs < 1 || p->n_rhs > 65535) return fail(GBS_EINVAL, "n_rhs out of range");
   const int r = p->fd_order / 2;
@@ -166,10 +179,15 @@ int levels_per_seq(const gbs_problem* p) { return p->op == GBS_ACOUSTIC2D ? 4 : 
 constexpr size_t kSrcBytes = (GBS_MAX_SRC * sizeof(SrcDesc) + kAlign - 1) / kAlign * kAlign;
 constexpr size_t kRecBytes = (GBS_MAX_REC * sizeof(RecDesc) + kAlign - 1) / kAlign * kAlign;
 
+// b_1..b_K of the Fourier derivative, K = (n-1)/2 (fourier_dsum)
+size_t fourier_bytes(const gbs_problem* p) {
+  return p->fd_order == GBS_FD_SPECTRAL ? align_up((size_t)((p->n[0] - 1) / 2) * 8) : 0;
+}
+
 size_t workspace_bytes(const gbs_problem* p, int k) {
   const int64_t pts = p->n[0] * p->n[1] * p->n[2];
   const size_t elems = (size_t)p->n_rhs * fields_of(p->op) * pts;
-  return kSrcBytes + kRecBytes + align_up(elems * 8) +
+  return kSrcBytes + kRecBytes + fourier_bytes(p) + align_up(elems * 8) +
          levels_per_seq(p) * (size_t)k * align_up(elems * dsize(p->dtype));
 }
 
@@ -231,6 +249,41 @@ double rho_of(const gbs_problem* prob) {
   return cmax * stencil_sigma(prob->fd_order) * std::sqrt(s2);
 }
 
+// Weights b_1..b_K of the Fourier derivative as a centred difference over
+// the whole period (fourier_dsum): b_k = pi (-1)^(k+1) cot(pi k / n) for even
+// n, pi (-1)^(k+1) / sin(pi k / n) for odd n (the periodic differentiation
+// matrix of the trigonometric interpolant, scaled to period 1).
+void fourier_weights(gbs_plan* P) {
+  const int64_t n = P->prob.n[0];
+  const int K = (int)((n - 1) / 2);
+  const double pi = 3.14159265358979323846;
+  std::vector<double> b(K);
+  for (int k = 1; k <= K; ++k) {
+    const double t = pi * (double)k / (double)n;
+    const double v = n % 2 == 0 ? std::cos(t) / std::sin(t) : 1.0 / std::sin(t);
+    b[k - 1] = (k % 2 ? pi : -pi) * v;
+  }
+  if (P->prob.dtype == GBS_F64) {
+    P->fourier_host.resize(b.size() * sizeof(double));
+    std::memcpy(P->fourier_host.data(), b.data(), P->fourier_host.size());
+  } else {
+    std::vector<float> bf(b.begin(), b.end());
+    P->fourier_host.resize(bf.size() * sizeof(float));
+    std::memcpy(P->fourier_host.data(), bf.data(), P->fourier_host.size());
+  }
+}
+
+// The Fourier weights reach the workspace on the plan's stream before the
+// first step that reads them (plan creation itself makes no device call).
+int upload_fourier(gbs_plan* P) {
+  if (!P->fourier_dev || P->fourier_ready || P->fourier_host.empty()) return GBS_OK;
+  if (hipMemcpyAsync(P->fourier_dev, P->fourier_host.data(), P->fourier_host.size(),
+                     hipMemcpyHostToDevice, P->stream) != hipSuccess)
+    return fail(GBS_EDEVICE, "copy of the Fourier-derivative weights failed");
+  P->fourier_ready = true;
+  return GBS_OK;
+}
+
 double ricker(double t, double f0, double delay) {
   const double pi = 3.14159265358979323846;
   const double a = (pi * f0 * (t - delay)) * (pi * f0 * (t - delay));
@@ -255,6 +308,7 @@ void fill_geometry(const gbs_plan* P, Geometry& g, T& c2c, const T*& c2f, T& ix,
   g.nsrc = P->nsrc;
   g.field = P->field;
   g.state = P->state;
+  g.fourier = P->fourier_dev;
   const double den = P->prob.fd_order == 8 ? 840.0 : 12.0;
   ix = (T)((double)P->prob.n[0] / den);
   iy = (T)((double)P->prob.n[1] / den);
@@ -658,6 +712,8 @@ int dispatch_rk4(gbs_plan* P, double t0, int n, double h, const void* yin, void*
   const T* a = (const T*)yin;
   T* b = (T*)yout;
   const int op = P->prob.op;
+  if (P->prob.fd_order == GBS_FD_SPECTRAL)
+    return run_rk4<T, GBS_FD_SPECTRAL, OP_ADV1D>(P, t0, n, h, a, b);
   if (P->prob.fd_order == 4) {
     if (op == GBS_ADVECT1D) return run_rk4<T, 4, OP_ADV1D>(P, t0, n, h, a, b);
     if (op == GBS_ACOUSTIC2D) return run_rk4<T, 4, OP_AC2D>(P, t0, n, h, a, b);
@@ -689,6 +745,7 @@ int dispatch_order(gbs_plan* P, double t0, int n, const void* yin, void* yout) {
       default: return run_temporal<T, 4, 7, false, 1>(P, t0, n, a, b);
     }
   }
+  if (P->prob.fd_order == GBS_FD_SPECTRAL) return run<T, GBS_FD_SPECTRAL, OP_ADV1D>(P, t0, n, a, b);
   if (P->prob.fd_order == 4) {
     if (op == GBS_ADVECT1D) return run<T, 4, OP_ADV1D>(P, t0, n, a, b);
     if (op == GBS_ACOUSTIC2D) return run<T, 4, OP_AC2D>(P, t0, n, a, b);
@@ -749,6 +806,11 @@ extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gb
     base += kSrcBytes;
     P->rec_dev = (RecDesc*)base;
     base += kRecBytes;
+    if (prob->fd_order == GBS_FD_SPECTRAL) {
+      fourier_weights(P);
+      P->fourier_dev = base;
+      base += fourier_bytes(prob);
+    }
     P->acc = (double*)base;
     base += align_up(elems * 8);
     const size_t lb = align_up(elems * dsize(prob->dtype));
@@ -809,6 +871,8 @@ extern "C" int gbs_step(gbs_plan* P, double t0, int32_t n_macro, const void* y_i
     }
     return GBS_OK;
   }
+  const int up = upload_fourier(P);
+  if (up) return up;
   if (P->prob.dtype == GBS_F64) return dispatch_order<double>(P, t0, n_macro, y_in, y_out);
   return dispatch_order<float>(P, t0, n_macro, y_in, y_out);
 }
@@ -832,6 +896,8 @@ extern "C" int gbs_rk4_step(gbs_plan* P, double t0, int32_t n_steps, double h, c
     }
     return GBS_OK;
   }
+  const int up = upload_fourier(P);
+  if (up) return up;
   if (P->prob.dtype == GBS_F64) return dispatch_rk4<double>(P, t0, n_steps, h, y_in, y_out);
   return dispatch_rk4<float>(P, t0, n_steps, h, y_in, y_out);
 }

@@ -73,6 +73,26 @@ __device__ __forceinline__ T dsum32(const T* __restrict__ f, uint32_t c, int i, 
   return acc;
 }
 
+// Fourier derivative on n points of [0,1) written as a centred difference
+// over the whole period: D u_i = sum_{k=1..K} b_k (u[i+k] - u[i-k]), K =
+// (n-1)/2, b_k = pi (-1)^(k+1) cot(pi k / n) for even n (the mode n/2 drops
+// out: cot(pi/2) = 0) and pi (-1)^(k+1) / sin(pi k / n) for odd n; `b` holds
+// b_1..b_K.  Pairing u[i+k] with u[i-k] keeps the large weights of small k
+// on differences of nearby values.
+template <typename T>
+__device__ __forceinline__ T fourier_dsum(const T* __restrict__ u, int i, int n,
+                                          const T* __restrict__ b) {
+  const int K = (n - 1) / 2;
+  T acc = T(0);
+  int up = i, dn = i;
+  for (int k = 1; k <= K; ++k) {
+    up = up + 1 == n ? 0 : up + 1;
+    dn = dn == 0 ? n - 1 : dn - 1;
+    acc += b[k - 1] * (u[up] - u[dn]);
+  }
+  return acc;
+}
+
 // Mode bits of one sequence in one leap-frog launch.
 enum : int32_t {
   MODE_LAST = 1,    // s == N_j: average, combine, no level written
@@ -128,6 +148,7 @@ struct Geometry {
   int32_t nsrc;
   int64_t field;   // points per field
   int64_t state;   // elements per right-hand side (F * field)
+  const void* fourier;   // Fourier-derivative weights b_k in the state's type, or null
 };
 
 template <typename T>

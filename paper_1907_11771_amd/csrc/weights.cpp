@@ -218,8 +218,11 @@ double isb_of(int k, const int32_t* steps, const std::vector<Rational>& c) {
 }
 
 // max over theta in [0, pi] of s(theta) = 2 sum_k a_k sin(k theta) for the
-// order-4 and order-8 centred stencils: dense scan, then golden section.
+// order-4 and order-8 centred stencils: dense scan, then golden section.  For
+// the Fourier derivative the symbol is theta itself (mode k: 2 pi k = theta n
+// with theta = 2 pi k / n), whose bound over the modes is pi.
 double stencil_sigma(int fd_order) {
+  if (fd_order == GBS_FD_SPECTRAL) return 3.14159265358979323846;
   const double a4[2] = {2.0 / 3.0, -1.0 / 12.0};
   const double a8[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
   const double* a = fd_order == 8 ? a8 : a4;

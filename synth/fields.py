@@ -20,6 +20,13 @@ def advection_modes(m, n_modes=8, kmax=16, seed=0):
     return u.reshape(1, m)
 
 
+def oneway_initial(m):
+    """u(x, 0) = (1 - cos 2 pi x) / 2 at x_i = i / m, shape (1, m): the
+    initial data of the one-way wave experiment (Sect. 4.1)."""
+    x = np.arange(m) / m
+    return (0.5 * (1.0 - np.cos(2.0 * np.pi * x))).reshape(1, m)
+
+
 def acoustic2d_pulse_modes(n, n_modes=32, kmax=16, width=0.02, seed=0):
     """Pressure = Gaussian pulse exp(-|x - x0|^2 / (2 w^2)) at x0 = (1/2, 1/2)
     (periodic distance) plus ``n_modes`` plane waves with distinct nonzero

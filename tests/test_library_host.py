@@ -267,3 +267,35 @@ def test_rk4_entry_validates_on_host():
         assert L.gbs_rk4_step(h, 0.0, 0, 0.5 * lim, ptr, ptr) == B.GBS_OK
     finally:
         B.plan_destroy(h)
+
+
+def test_fourier_derivative_plans_on_host():
+    # spectral advection (Sect. 4.1): rho = pi M; ADVECT1D only; 4 <= M <= 8192
+    steps, w = _cfg2()
+    sc = B.make_scheme(8, steps, w)
+    for op, n in ((B.ACOUSTIC2D, (32, 32)), (B.ACOUSTIC3D, (16, 16, 16))):
+        with pytest.raises(B.GBSError) as ei:
+            B.workspace_bytes(B.make_problem(op, n, fd_order=B.FD_SPECTRAL), sc)
+        assert ei.value.status == B.GBS_EUNSUPPORTED
+    for m in (3, 8193):
+        with pytest.raises(B.GBSError) as ei:
+            B.workspace_bytes(B.make_problem(B.ADVECT1D, (m,), fd_order=B.FD_SPECTRAL), sc)
+        assert ei.value.status == B.GBS_EINVAL
+    m = 100
+    pr = B.make_problem(B.ADVECT1D, (m,), fd_order=B.FD_SPECTRAL)
+    fd = B.make_problem(B.ADVECT1D, (m,), fd_order=4)
+    nb = B.workspace_bytes(pr, sc)
+    assert nb == B.workspace_bytes(fd, sc) + 512      # the 49 weights b_k (392 B), 256-aligned
+    isb = B.isb(steps, w)
+    lim = isb / (3.141592653589793 * m)
+    B.plan_destroy(B.plan_create(pr, sc, 0.999 * lim, FAKE_WS, nb))
+    with pytest.raises(B.GBSError) as ei:
+        B.plan_create(pr, sc, 1.001 * lim, FAKE_WS, nb)
+    assert ei.value.status == B.GBS_EUNSTABLE
+    h = B.plan_create(pr, sc, 0.5 * lim, FAKE_WS, nb)
+    ptr = ctypes.c_void_p(FAKE_WS)
+    try:
+        rk_lim = 2 * 2 ** 0.5 / (3.141592653589793 * m)
+        assert B.lib().gbs_rk4_step(h, 0.0, 1, 1.001 * rk_lim, ptr, ptr) == B.GBS_EUNSTABLE
+    finally:
+        B.plan_destroy(h)

@@ -126,3 +126,16 @@ def test_printed_error_floors_of_truncated_weights():
             assert e_more <= full * 10, (sch["name"], m, e_more)
             errs.append(e16)
         assert errs[-1] >= errs[0]                   # refinement no longer helps
+
+
+def test_closed_form_solution_agrees_with_its_error_and_the_literal_run():
+    sch = schemes.GBS_8_6
+    steps = list(sch["steps"])
+    c = W.to_fp64(_exact(sch))
+    m = 24
+    n, _ = O.macro_steps(m, _isb(sch))
+    poly = O.gbs_poly(steps, c)
+    u = O.solution_closed_form(m, poly, n)
+    assert abs(np.max(np.abs(u - O.initial(m))) - O.error_closed_form(m, poly, n)) <= 1e-15
+    lit, _ = O.run(m, steps, c, n)
+    assert np.max(np.abs(lit - u)) <= 1e-13
