@@ -56,9 +56,63 @@ def cpu_baseline(cfg, y0):
     G.macro_step(op, 0.0, y0, cfg["H"], steps, c)
     dt = time.perf_counter() - t
     updates = cfg["n"] * cfg["n"] * (1 + sum(steps))
-    return dict(value=updates / dt, unit="grid-pt RHS updates/s", cores=1, kind="oracle",
-                sample="1 macro step of the same 2048^2 FP64 workload (43 RHS sweeps), "
-                       "%.1f s, NumPy single thread" % dt)
+    out = dict(value=updates / dt, unit="grid-pt RHS updates/s", cores=1, kind="oracle",
+               sample="1 macro step of the same 2048^2 FP64 workload (43 RHS sweeps), "
+                      "%.1f s, NumPy single thread" % dt)
+    out["folded"] = cpu_folded(cfg, updates)
+    return out
+
+
+def _folded_group(args):
+    """One process of the paper's CPU scheme: its sequences of one macro step
+    of the oracle, on the same synthetic state (regenerated from its seed);
+    returns the seconds of compute (the group's sum c_j y*_j stays local)."""
+    cfg, group = args
+    import numpy as np
+    from oracle import gbs as G
+    from oracle import operators as OP
+    from synth import fields
+    y0 = fields.acoustic2d_pulse_modes(cfg["n"])
+    op = OP.Acoustic((cfg["n"], cfg["n"]), c2=cfg["c2"], r=cfg["r"])
+    t = time.perf_counter()
+    f0 = op(0.0, y0)
+    part = None
+    for n, cj in group:
+        term = cj * G.sequence(op, 0.0, y0, f0, cfg["H"] / n, n)
+        part = term if part is None else part + term
+    return time.perf_counter() - t
+
+
+def cpu_folded(cfg, updates):
+    """The paper's own CPU scheme (Sect. 3.6) as a second reference: the
+    sequences folded in pairs whose step counts add up to N_max, one process
+    per group ({12}, {10, 2}, {8, 4}, {6}), each evaluating f(t0, y0) itself;
+    the time of one macro step is the slowest group's.  Processes are started
+    with the spawn method (fresh interpreters that touch no device)."""
+    import multiprocessing as mp
+    from fractions import Fraction
+    from oracle import weights as W
+    sch = cfg["scheme"]
+    exact = W.weights(sch["p"], sch["steps"], sch["free_idx"], [Fraction(x) for x in sch["c_free"]])
+    pairs = dict(zip(sch["steps"], W.to_fp64(exact)))
+    ns = sorted(pairs)
+    groups, lo, hi = [], 0, len(ns) - 1
+    while lo <= hi:
+        g = [ns[hi]] if lo == hi or ns[hi] == max(ns) else [ns[hi], ns[lo]]
+        if len(g) == 2:
+            lo += 1
+        hi -= 1
+        groups.append([(n, pairs[n]) for n in g])
+    try:
+        with mp.get_context("spawn").Pool(len(groups)) as pool:
+            res = pool.map_async(_folded_group, [(cfg, g) for g in groups]).get(timeout=300)
+    except Exception as e:                            # report, never hang the bench
+        return dict(error="folded CPU reference failed: %r" % (e,))
+    dt = max(res)
+    return dict(value=updates / dt, unit="grid-pt RHS updates/s", cores=len(groups),
+                kind="oracle, folded sequences",
+                sample="the same macro step, groups %s, one process each, %.2f s (slowest group)"
+                       % ([[n for n, _ in g] for g in groups], dt))
 
 
 def bench_batch(args):
