@@ -78,19 +78,25 @@ __device__ __forceinline__ T dsum32(const T* __restrict__ f, uint32_t c, int i, 
 // (n-1)/2, b_k = pi (-1)^(k+1) cot(pi k / n) for even n (the mode n/2 drops
 // out: cot(pi/2) = 0) and pi (-1)^(k+1) / sin(pi k / n) for odd n; `b` holds
 // b_1..b_K.  Pairing u[i+k] with u[i-k] keeps the large weights of small k
-// on differences of nearby values.
+// on differences of nearby values.  The K terms are summed with Kahan's
+// compensation: a plain running sum of this many terms loses about sqrt(K)
+// ulps on grid-scale data (8e-15 relative at n = 8192, against 4e-16 for an
+// FFT), the compensated one stays near one ulp.
 template <typename T>
 __device__ __forceinline__ T fourier_dsum(const T* __restrict__ u, int i, int n,
                                           const T* __restrict__ b) {
   const int K = (n - 1) / 2;
-  T acc = T(0);
+  T sum = T(0), comp = T(0);
   int up = i, dn = i;
   for (int k = 1; k <= K; ++k) {
     up = up + 1 == n ? 0 : up + 1;
     dn = dn == 0 ? n - 1 : dn - 1;
-    acc += b[k - 1] * (u[up] - u[dn]);
+    const T y = b[k - 1] * (u[up] - u[dn]) - comp;
+    const T t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
   }
-  return acc;
+  return sum;
 }
 
 // Mode bits of one sequence in one leap-frog launch.

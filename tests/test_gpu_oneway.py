@@ -103,3 +103,20 @@ def test_fp32_stepping():
     print("fp32 vs fp64 after one revolution", err)
     # FP32 levels: rounding 6e-8 per level, amplified by sum |c| = 31
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("m,n_macro", [(4, 3), (5, 3), (8192, 2)])
+def test_smallest_and_largest_grids(m, n_macro):
+    # 4 and 5 points: one weight b_1 (K = 1, resp. 2); 8192: the largest grid
+    # the Fourier derivative accepts; random data, a few macro steps
+    sch = schemes.GBS_8_6
+    n, _ = O.macro_steps(m, _isb(sch))
+    plan, steps, w = _plan(sch, m, n)
+    y0 = np.random.default_rng(m).standard_normal((1, m))
+    got = plan.step(to_dev(y0[None]), n_macro=n_macro).cpu().numpy()[0]
+    from oracle import gbs as G
+    from oracle import operators as OP
+    want = G.integrate(OP.SpectralAdvection1D(m), 0.0, y0, 1.0 / n, n_macro, steps, w)
+    err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    print("M", m, "rel err", err)
+    assert err <= 1e-12
