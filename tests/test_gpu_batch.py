@@ -97,8 +97,8 @@ def test_batch_autotune_picks_a_candidate():
     batch = GBSBatch(inst, 8, steps, w)
     v, band = batch.autotune(_states(torch.float64), macro_steps=1)
     assert v in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
-                 B.VARIANT_TEMPORAL_WG4, B.VARIANT_TEMPORAL_WG8)
-    assert band in (32, 64, 128)
+                 B.VARIANT_TEMPORAL_S6, B.VARIANT_TEMPORAL_WG4, B.VARIANT_TEMPORAL_WG8)
+    assert band in (32, 64, 96, 128)
     ys = _states(torch.float64, seed=3)
     ref = [y.clone() for y in ys]
     batch.step(ys, n_macro=1)
