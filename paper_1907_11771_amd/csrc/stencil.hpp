@@ -87,10 +87,12 @@ __device__ __forceinline__ T fourier_dsum(const T* __restrict__ u, int i, int n,
                                           const T* __restrict__ b) {
   const int K = (n - 1) / 2;
   T sum = T(0), comp = T(0);
-  int up = i, dn = i;
+  // unrolled so that the loads of several k are in flight at once (the
+  // compensated sum itself is a dependent chain)
+#pragma unroll 8
   for (int k = 1; k <= K; ++k) {
-    up = up + 1 == n ? 0 : up + 1;
-    dn = dn == 0 ? n - 1 : dn - 1;
+    const int up = i + k < n ? i + k : i + k - n;
+    const int dn = i - k >= 0 ? i - k : i - k + n;
     const T y = b[k - 1] * (u[up] - u[dn]) - comp;
     const T t = sum + y;
     comp = (t - sum) - y;
