@@ -352,6 +352,29 @@ int gbs_adjoint_step(gbs_plan* plan, double t0, const void* y_in, void* ybar,
                      size_t adj_workspace_bytes);
 
 /*
+ * Kept forward levels for the temporally blocked adjoint (2-D FD4 operator
+ * with a temporally blocked variant; GBS_EUNSUPPORTED otherwise, checked
+ * before any device work).  Trades memory for the forward passes that
+ * gbs_adjoint_step runs to rebuild (y_{N_j - 1}, y_{N_j}) of every sequence:
+ *
+ * gbs_step_keep_pairs — as gbs_step (n_macro >= 1), and the final pass of
+ *   every sequence also writes its last two leap-frog levels into `pairs`
+ *   (device, caller-owned, in the plan's dtype), laid out
+ *   [n_macro][k][2][R][F][Y][X]: macro step m, sequence j in the order of
+ *   the scheme's steps[], then y_{N_j - 1} and y_{N_j}, each a whole state
+ *   (2 k R F n_x n_y elements per macro step).
+ * gbs_adjoint_step_pairs — as gbs_adjoint_step for the macro step starting
+ *   at (t0, y_in), with `pairs` (device, read only) the [k][2][state] block
+ *   that gbs_step_keep_pairs wrote for that macro step from the same y_in,
+ *   t0 and plan settings; the result equals gbs_adjoint_step's.
+ */
+int gbs_step_keep_pairs(gbs_plan* plan, double t0, int32_t n_macro, const void* y_in,
+                        void* y_out, void* pairs);
+int gbs_adjoint_step_pairs(gbs_plan* plan, double t0, const void* y_in, const void* pairs,
+                           void* ybar, const void* trace_bar, double* grad_c2,
+                           void* adj_workspace, size_t adj_workspace_bytes);
+
+/*
  * Batches of independent 2-D acoustic instances (GBS_ACOUSTIC2D, n_rhs = 1,
  * no sources), each with its own grid size, coefficient (constant c^2 or a
  * c^2 field) and macro step H[i], one common scheme, dtype and stencil

@@ -90,6 +90,8 @@ def lib():
             "gbs_step_record": [vp, dbl, i32, vp, vp, vp],
             "gbs_plan_adjoint_workspace_bytes": [vp, P(sz)],
             "gbs_adjoint_step": [vp, dbl, vp, vp, vp, vp, vp, sz],
+            "gbs_step_keep_pairs": [vp, dbl, i32, vp, vp, vp],
+            "gbs_adjoint_step_pairs": [vp, dbl, vp, vp, vp, vp, vp, vp, sz],
             "gbs_batch_workspace_bytes": [i32, P(Problem), P(Scheme), P(sz)],
             "gbs_batch_plan_create": [P(vp), i32, P(Problem), P(Scheme), P(dbl), vp, sz, vp],
             "gbs_batch_set_variant": [vp, i32, i32],

@@ -86,6 +86,9 @@ struct gbs_plan {
   int band = 0;            // 0: chosen per launch
   // temporally blocked layout: per sequence two pairs of levels
   void* pair[GBS_MAX_SEQ][2][2];
+  // gbs_step_keep_pairs: caller's buffer for (y_{N-1}, y_N) of every
+  // sequence and macro step, set for the duration of that call only
+  void* keep_out = nullptr;
   // the blocked passes of one macro step spread over `lanes` streams (the
   // plan's stream and lanes - 1 streams of its own), joined before the
   // combination
@@ -499,6 +502,13 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         d.out_a = (T*)P->pair[j][q % 2][0];
         d.out_b = (T*)P->pair[j][q % 2][1];
         d.ystar = (double*)P->pair[j][q % 2][0];
+        if (P->keep_out && q == npass[j] - 1) {
+          // [macro step][sequence j][y_{N-1}, y_N][whole state]
+          T* kb = (T*)P->keep_out + ((size_t)m * P->k + j) * 2 * ca.n;
+          d.flags |= PASS_KEEP;
+          d.out_a = kb;
+          d.out_b = kb + ca.n;
+        }
         d.strips = (nx + (64 * WPG - 2 * d.g * R) - 1) / (64 * WPG - 2 * d.g * R);
         for (int e = 0; e < d.g; ++e)
           d.amp[e] = P->nsrc ? ricker(t + (s0 + e) * h, P->f0, P->delay) : 0.0;
@@ -523,6 +533,18 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
       }
       const unsigned blocks = WPG > 1 ? waves : (waves + 3) / 4;
       const dim3 grid(blocks, n, P->prob.n_rhs), blk(WPG > 1 ? 64 * WPG : 256);
+      // the kept-pairs stores live in their own instantiations so that the
+      // plain forward kernels keep their register budget
+      if constexpr (ORDER == 4) {
+        if (P->keep_out) {
+          if (P->prob.c2_field)
+            hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, true, true>), grid, blk, 0, ls, pa);
+          else
+            hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, false, true>), grid, blk, 0, ls, pa);
+          if (ev) hipEventRecord(ev->b, ls);
+          continue;
+        }
+      }
       if (P->prob.c2_field)
         hipLaunchKernelGGL((pass2d<T, ORDER, G, SKEW1, WPG, true>), grid, blk, 0, ls, pa);
       else
@@ -1721,7 +1743,7 @@ __global__ __launch_bounds__(256) void adj_sum_kernel(const AdjSumArgs<T> a) {
 
 template <typename T>
 int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar,
-                        double* grad, char* ws) {
+                        double* grad, char* ws, const T* kept = nullptr) {
   constexpr int ORDER = 4, R = 2;
   constexpr int G = adj_pass_g<T>();
   const size_t elems = (size_t)P->prob.n_rhs * P->state;
@@ -1758,15 +1780,24 @@ int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* t
   int st = make_schedule(P->steps, P->k, G, R, 1, sch, false, 0);
   if (st) return st;
   const T* pairs[GBS_MAX_SEQ][2];
+  if (kept) {
+    // (y_{N-1}, y_N) kept by gbs_step_keep_pairs: [sequence j][2][whole state]
+    for (int j = 0; j < P->k; ++j) {
+      pairs[j][0] = kept + (size_t)(2 * j) * elems;
+      pairs[j][1] = kept + (size_t)(2 * j + 1) * elems;
+    }
+  }
   for (int l = 0; l < L; ++l) {
     const hipStream_t ls = l == 0 ? s : P->lane_stream[l];
     // the forward pairs with the pass shape of the plan's forward form
     // (its evaluations per pass and time skew; one wavefront per strip)
-    switch (temporal_shape(resolve_variant(P), 4).G) {
-      case 4: st = forward_pairs<T, 4, false>(P, t0, y0, pairs, lane_of, l, L, ls); break;
-      case 5: st = forward_pairs<T, 5, true>(P, t0, y0, pairs, lane_of, l, L, ls); break;
-      case 6: st = forward_pairs<T, 6, true>(P, t0, y0, pairs, lane_of, l, L, ls); break;
-      default: st = forward_pairs<T, 7, false>(P, t0, y0, pairs, lane_of, l, L, ls); break;
+    if (!kept) {
+      switch (temporal_shape(resolve_variant(P), 4).G) {
+        case 4: st = forward_pairs<T, 4, false>(P, t0, y0, pairs, lane_of, l, L, ls); break;
+        case 5: st = forward_pairs<T, 5, true>(P, t0, y0, pairs, lane_of, l, L, ls); break;
+        case 6: st = forward_pairs<T, 6, true>(P, t0, y0, pairs, lane_of, l, L, ls); break;
+        default: st = forward_pairs<T, 7, false>(P, t0, y0, pairs, lane_of, l, L, ls); break;
+      }
     }
     if (st) return st;
     AdjPassArgs<T> pa;
@@ -2006,9 +2037,10 @@ extern "C" int gbs_plan_adjoint_workspace_bytes(const gbs_plan* P, size_t* bytes
   return GBS_OK;
 }
 
-extern "C" int gbs_adjoint_step(gbs_plan* P, double t0, const void* y_in, void* ybar,
-                                const void* trace_bar, double* grad_c2, void* adj_ws,
-                                size_t adj_ws_bytes) {
+namespace {
+
+int check_adjoint_args(const gbs_plan* P, double t0, const void* y_in, const void* ybar,
+                       double* grad_c2, const void* adj_ws, size_t adj_ws_bytes) {
   if (!P || !y_in || !ybar || !adj_ws) return fail(GBS_EINVAL, "null argument");
   if (P->prob.op == GBS_ADVECT1D) return fail(GBS_EUNSUPPORTED, "the adjoint is built for the acoustic operators");
   if (grad_c2 && !P->prob.c2_field)
@@ -2018,7 +2050,48 @@ extern "C" int gbs_adjoint_step(gbs_plan* P, double t0, const void* y_in, void* 
     return fail(GBS_ENOMEM, "adjoint workspace has %zu bytes, needs %zu", adj_ws_bytes,
                 adjoint_bytes(P));
   if (!std::isfinite(t0)) return fail(GBS_EINVAL, "t0 must be finite");
+  return GBS_OK;
+}
+
+}  // namespace
+
+extern "C" int gbs_adjoint_step(gbs_plan* P, double t0, const void* y_in, void* ybar,
+                                const void* trace_bar, double* grad_c2, void* adj_ws,
+                                size_t adj_ws_bytes) {
+  const int st = check_adjoint_args(P, t0, y_in, ybar, grad_c2, adj_ws, adj_ws_bytes);
+  if (st) return st;
   if (P->prob.dtype == GBS_F64)
     return adjoint_dispatch<double>(P, t0, y_in, ybar, trace_bar, grad_c2, (char*)adj_ws);
   return adjoint_dispatch<float>(P, t0, y_in, ybar, trace_bar, grad_c2, (char*)adj_ws);
+}
+
+extern "C" int gbs_step_keep_pairs(gbs_plan* P, double t0, int32_t n_macro, const void* y_in,
+                                   void* y_out, void* pairs) {
+  if (!P || !y_in || !y_out || !pairs) return fail(GBS_EINVAL, "null argument");
+  if (n_macro < 1) return fail(GBS_EINVAL, "n_macro must be >= 1");
+  if (!blocked_adjoint(P))
+    return fail(GBS_EUNSUPPORTED,
+                "kept pairs need the 2-D FD4 operator with a temporally blocked variant");
+  P->keep_out = pairs;
+  const int st = gbs_step(P, t0, n_macro, y_in, y_out);
+  P->keep_out = nullptr;
+  return st;
+}
+
+extern "C" int gbs_adjoint_step_pairs(gbs_plan* P, double t0, const void* y_in,
+                                      const void* pairs, void* ybar, const void* trace_bar,
+                                      double* grad_c2, void* adj_ws, size_t adj_ws_bytes) {
+  int st = check_adjoint_args(P, t0, y_in, ybar, grad_c2, adj_ws, adj_ws_bytes);
+  if (st) return st;
+  if (!pairs) return fail(GBS_EINVAL, "null argument");
+  if (!blocked_adjoint(P))
+    return fail(GBS_EUNSUPPORTED,
+                "kept pairs need the 2-D FD4 operator with a temporally blocked variant");
+  if (P->prob.dtype == GBS_F64)
+    return adjoint_blocked_run<double>(P, t0, (const double*)y_in, (double*)ybar,
+                                       (const double*)trace_bar, grad_c2, (char*)adj_ws,
+                                       (const double*)pairs);
+  return adjoint_blocked_run<float>(P, t0, (const float*)y_in, (float*)ybar,
+                                    (const float*)trace_bar, grad_c2, (char*)adj_ws,
+                                    (const float*)pairs);
 }

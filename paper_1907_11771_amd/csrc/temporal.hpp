@@ -27,14 +27,16 @@ namespace gbs {
 
 constexpr int PASS_FIRST = 1;   // input is y_0; evaluation 1 is forward Euler
 constexpr int PASS_FINAL = 2;   // output is y* (FP64) instead of two levels
+constexpr int PASS_KEEP = 4;    // final pass also stores (y_{N-1}, y_N) to out_a, out_b
+                                // (only in kernels instantiated with KEEP = true)
 constexpr int PASS_GMAX = 8;
 
 template <typename T>
 struct PassSeq {
   const T* old;       // later pass: y_{s-1}
   const T* cur;       // later pass: y_s; first pass: y_0
-  T* out_a;           // non-final: A_{g-1}
-  T* out_b;           // non-final: A_g
+  T* out_a;           // non-final: A_{g-1}; final with PASS_KEEP: y_{N-1}
+  T* out_b;           // non-final: A_g; final with PASS_KEEP: y_N
   double* ystar;      // final: y* (FP64, state-sized)
   T h;                // substep h_j
   int32_t g;          // evaluations in this pass (1..G)
@@ -157,7 +159,7 @@ __device__ __forceinline__ T lane_dsum_edges(T u, int lane, const T* left, const
   return s;
 }
 
-template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC>
+template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC, bool KEEP = false>
 __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, const int band) {
   constexpr int R = Fd<ORDER>::R;
   constexpr int S = SKEW1 ? R + 1 : R;               // rows between consecutive levels
@@ -184,6 +186,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
   const int64_t F1 = w.field, F2 = 2 * w.field;
   const bool first = w.flags & PASS_FIRST;
   const bool final_ = w.flags & PASS_FINAL;
+  const bool keep = KEEP && (w.flags & PASS_KEEP);   // compiled only where asked for
   constexpr bool varc = VARC;                       // c^2 field (else the constant)
   const LaneSource ls = w.nsrc > 0 ? lane_source(w.src, w.nsrc, w.rhs, gx, nx) : LaneSource();
   const bool srcs = ls.any;
@@ -329,6 +332,10 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
                 const T ym1 = (e >= 2) ? W[e >= 2 ? e - 2 : 0][c][q] : (first ? In[c][q] : om[q]);
                 w.ystar[pt + q * F1] =
                     0.25 * (((double)ym1 + 2.0 * (double)In[c][q]) + (double)nw[q]);
+                if (keep) {
+                  w.out_a[pt + q * F1] = ym1;
+                  w.out_b[pt + q * F1] = In[c][q];
+                }
               }
             }
           }
@@ -358,7 +365,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
 // arguments), blockIdx.z the right-hand side; a workgroup of WPG wavefronts
 // covers one (strip, band), or with WPG = 1 each wavefront of a 4-wave block
 // does.
-template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC>
+template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC, bool KEEP = false>
 __global__ __launch_bounds__(WPG > 1 ? 64 * WPG : 256) __attribute__((amdgpu_waves_per_eu(2)))
 void pass2d(const PassArgs<T> a) {
   const PassSeq<T>& d = a.seq[blockIdx.y];
@@ -390,7 +397,7 @@ void pass2d(const PassArgs<T> a) {
   w.nsrc = a.g.nsrc;
 #pragma unroll
   for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = d.amp[e];
-  pass_body<T, ORDER, G, SKEW1, WPG, VARC>(w, strip, band);
+  pass_body<T, ORDER, G, SKEW1, WPG, VARC, KEEP>(w, strip, band);
 }
 
 // A batch of problems: the passes of one round of every (instance, sequence)

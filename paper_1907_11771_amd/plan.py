@@ -9,6 +9,8 @@ from . import binding as B
 
 _DT = {torch.float64: B.F64, torch.float32: B.F32}
 _FIELDS = {B.ADVECT1D: 1, B.ACOUSTIC2D: 3, B.ACOUSTIC3D: 4}
+_TEMPORAL = (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
+             B.VARIANT_TEMPORAL_S6, B.VARIANT_TEMPORAL_WG4, B.VARIANT_TEMPORAL_WG8)
 
 
 def scheme_weights(scheme):
@@ -140,6 +142,44 @@ class GBSPlan:
                                          ws.data_ptr(), ws.numel()))
         return ybar
 
+    def pairs_shape(self, n_macro=1):
+        """Shape of the buffer gbs_step_keep_pairs fills: [n_macro][k][2] whole
+        states (the last two leap-frog levels of every sequence)."""
+        return (n_macro, len(self.steps), 2) + self.state_shape
+
+    def step_keep_pairs(self, y, out, pairs, t0=0.0, n_macro=1):
+        """As step(), also keeping (y_{N-1}, y_N) of every sequence and macro
+        step in ``pairs`` (shape pairs_shape(n_macro), the plan's dtype)."""
+        self._check_state(y)
+        self._check_state(out)
+        if (pairs.device != self.device or pairs.dtype != self.dtype
+                or not pairs.is_contiguous() or tuple(pairs.shape) != self.pairs_shape(n_macro)):
+            raise ValueError("pairs must be a contiguous %s tensor of shape %s"
+                             % (self.dtype, self.pairs_shape(n_macro)))
+        B.check(B.lib().gbs_step_keep_pairs(self.handle, float(t0), int(n_macro), y.data_ptr(),
+                                            out.data_ptr(), pairs.data_ptr()))
+        return out
+
+    def adjoint_step_pairs(self, t0, y_in, pairs, ybar, trace_bar=None, grad_c2=None):
+        """adjoint_step() with the forward levels kept by step_keep_pairs
+        (``pairs``: that macro step's [k][2] block) instead of recomputed."""
+        self._check_state(y_in)
+        self._check_state(ybar)
+        if (pairs.device != self.device or pairs.dtype != self.dtype
+                or not pairs.is_contiguous() or tuple(pairs.shape) != self.pairs_shape(1)[1:]):
+            raise ValueError("pairs must be one macro step's contiguous block %s"
+                             % (self.pairs_shape(1)[1:],))
+        if trace_bar is not None:
+            trace_bar = trace_bar.to(self.dtype).contiguous()
+        if grad_c2 is not None and (grad_c2.dtype != torch.float64 or not grad_c2.is_contiguous()):
+            raise ValueError("grad_c2 must be a contiguous float64 tensor")
+        ws = self.adjoint_workspace()
+        B.check(B.lib().gbs_adjoint_step_pairs(
+            self.handle, float(t0), y_in.data_ptr(), pairs.data_ptr(), ybar.data_ptr(),
+            trace_bar.data_ptr() if trace_bar is not None else None,
+            grad_c2.data_ptr() if grad_c2 is not None else None, ws.data_ptr(), ws.numel()))
+        return ybar
+
     def set_variant(self, variant):
         B.check(B.lib().gbs_plan_set_variant(self.handle, int(variant)))
 
@@ -165,6 +205,13 @@ class GBSPlan:
         out = ctypes.c_int32()
         B.check(B.lib().gbs_plan_get_variant(self.handle, ctypes.byref(out)))
         return out.value
+
+    def blocked_adjoint(self):
+        """Whether gbs_adjoint_step takes the temporally blocked form (2-D
+        FD4 with a temporally blocked forward variant), the one that can use
+        kept pairs."""
+        return (self.op == B.ACOUSTIC2D and self.problem.fd_order == 4
+                and self.variant() in _TEMPORAL)
 
     def set_timing(self, on):
         """on: bool, or the number of macro steps to create events for."""

@@ -238,3 +238,72 @@ def test_blocked_adjoint_lanes_do_not_change_the_result():
         plan.adjoint_step(0.9 * s["delay"], y0, ybar, grad_c2=grad)
         res.append((ybar.clone(), grad.clone()))
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("variant,lanes", [(B.VARIANT_TEMPORAL_S5, 1), (B.VARIANT_TEMPORAL, 2)])
+def test_kept_pairs_give_the_same_adjoint(dtype, variant, lanes):
+    # the forward step that keeps (y_{N-1}, y_N) returns the same state, and
+    # the adjoint from the kept levels equals the one that rebuilds them
+    ny, nx = 150, 130
+    cs = fields.lognormal_speed((ny, nx), seed=20)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(nx, ny), 2,
+                           workloads.SIGMA_FD4)
+    rng = np.random.default_rng(21)
+    y0 = to_dev(rng.standard_normal((2, 3, ny, nx)), dtype)
+    wbar = rng.standard_normal((2, 3, ny, nx))
+    s = fields.ricker_source_2d(max(nx, ny), cells_per_wavelength=6.0)
+    plan = lib_plan(B.ACOUSTIC2D, (nx, ny), schemes.ORDER8_K6, H, n_rhs=2, dtype=dtype,
+                    c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
+    plan.set_sources([1], [70 * nx + 40], [s["weight"] * 1e-3], s["f0"], s["delay"])
+    plan.set_variant(variant)
+    plan.set_lanes(lanes)
+    t0 = 0.9 * s["delay"]
+    n_macro = 3
+    pairs = torch.empty(plan.pairs_shape(n_macro), dtype=dtype, device="cuda")
+    y_keep = torch.empty_like(y0)
+    plan.step_keep_pairs(y0, y_keep, pairs, t0=t0, n_macro=n_macro)
+    states = [y0.clone()]
+    for m in range(n_macro):
+        states.append(plan.step(states[-1], t0=t0 + m * H))
+    assert torch.equal(y_keep, states[-1])
+    for m in range(n_macro):
+        res = []
+        for kept in (False, True):
+            ybar = to_dev(wbar, dtype)
+            grad = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+            if kept:
+                plan.adjoint_step_pairs(t0 + m * H, states[m], pairs[m], ybar, grad_c2=grad)
+            else:
+                plan.adjoint_step(t0 + m * H, states[m], ybar, grad_c2=grad)
+            res.append((ybar, grad))
+        assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1]), m
+
+
+def test_checkpointed_gradient_with_kept_pairs():
+    plan, op, H = _setup2d(nx=64, ny=48)
+    nx, ny = 64, 48
+    rec = fields.edge_receivers_2d(nx, count=8, row=3)
+    plan.set_receivers([0] * len(rec), [int(r[0]) * nx + int(r[1]) for r in rec])
+    n_macro = 9
+    y0 = fields.acoustic2d_pulse_modes(nx, n_modes=4, kmax=3, width=0.1, seed=8)[:, :ny, :]
+    data = to_dev(np.random.default_rng(5).standard_normal((n_macro, len(rec))) * 1e-2)
+    grads = []
+    for keep in (False, True):
+        y = to_dev(y0[None]).requires_grad_(True)
+        c2 = plan.c2_field.clone().requires_grad_(True)
+        tr = receiver_traces(plan, y, c2, n_macro, checkpoint_every=4, keep_pairs=keep)
+        (0.5 * ((tr - data) ** 2).sum()).backward()
+        grads.append((y.grad.clone(), c2.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+
+
+def test_kept_pairs_need_the_blocked_form():
+    plan, _, _ = _setup2d()
+    plan.set_variant(B.VARIANT_FLAT)
+    y = torch.zeros(plan.state_shape, dtype=torch.float64, device="cuda")
+    pairs = torch.empty(plan.pairs_shape(1), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.GBSError) as ei:
+        plan.step_keep_pairs(y, y.clone(), pairs)
+    assert ei.value.status == B.GBS_EUNSUPPORTED
+    assert not plan.blocked_adjoint()

@@ -299,3 +299,31 @@ def test_fourier_derivative_plans_on_host():
         assert B.lib().gbs_rk4_step(h, 0.0, 1, 1.001 * rk_lim, ptr, ptr) == B.GBS_EUNSTABLE
     finally:
         B.plan_destroy(h)
+
+
+def test_kept_pairs_validation_on_host():
+    # every rejection happens before any device call
+    steps, w = _cfg2()
+    sc = B.make_scheme(8, steps, w)
+    ptr = ctypes.c_void_p(FAKE_WS)
+    L = B.lib()
+    for fd, variant, want in ((8, 0, B.GBS_EUNSUPPORTED), (4, B.VARIANT_FLAT, B.GBS_EUNSUPPORTED)):
+        pr = B.make_problem(B.ACOUSTIC2D, (64, 32), fd_order=fd)
+        h = B.plan_create(pr, sc, 1e-4, FAKE_WS, B.workspace_bytes(pr, sc))
+        try:
+            if variant:
+                B.check(L.gbs_plan_set_variant(h, variant))
+            assert L.gbs_step_keep_pairs(h, 0.0, 1, ptr, ptr, ptr) == want
+            assert L.gbs_adjoint_step_pairs(h, 0.0, ptr, ptr, ptr, None, None, ptr,
+                                            1 << 40) == want
+        finally:
+            B.plan_destroy(h)
+    pr = B.make_problem(B.ACOUSTIC2D, (64, 32))
+    h = B.plan_create(pr, sc, 1e-4, FAKE_WS, B.workspace_bytes(pr, sc))
+    try:
+        assert L.gbs_step_keep_pairs(h, 0.0, 1, ptr, ptr, None) == B.GBS_EINVAL
+        assert L.gbs_step_keep_pairs(h, 0.0, 0, ptr, ptr, ptr) == B.GBS_EINVAL
+        assert L.gbs_adjoint_step_pairs(h, 0.0, ptr, None, ptr, None, None, ptr,
+                                        1 << 40) == B.GBS_EINVAL
+    finally:
+        B.plan_destroy(h)
