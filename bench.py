@@ -23,17 +23,17 @@ STREAM_BYTES_PER_UPDATE = 72.0   # FP64 2-D acoustic leap-frog update, streaming
 # the plain-copy calibration) for the kernel as it is now; see profiles/.  An
 # entry must be removed when its kernel changes.
 MEASURED_TRAFFIC_BYTES_PER_LAUNCH = {
-    "gbs::pass2d<double, 4, 5, true, 1, false>": 1.468e9,    # profiles/pass2d_acoustic2d_2048_fd4_f64.txt
+    "gbs::pass2d<double, 4, 5, true, 1, false, false>": 1.467e9,    # profiles/pass2d_acoustic2d_2048_fd4_f64.txt
 }
 
 
 def kernel_names(variant, B):
-    step = {B.VARIANT_TEMPORAL: "gbs::pass2d<double, 4, 7, false, 1, false>",
-            B.VARIANT_TEMPORAL4: "gbs::pass2d<double, 4, 4, false, 1, false>",
-            B.VARIANT_TEMPORAL_S5: "gbs::pass2d<double, 4, 5, true, 1, false>",
-            B.VARIANT_TEMPORAL_S6: "gbs::pass2d<double, 4, 6, true, 1, false>",
-            B.VARIANT_TEMPORAL_WG4: "gbs::pass2d<double, 4, 7, false, 4, false>",
-            B.VARIANT_TEMPORAL_WG8: "gbs::pass2d<double, 4, 7, false, 8, false>",
+    step = {B.VARIANT_TEMPORAL: "gbs::pass2d<double, 4, 7, false, 1, false, false>",
+            B.VARIANT_TEMPORAL4: "gbs::pass2d<double, 4, 4, false, 1, false, false>",
+            B.VARIANT_TEMPORAL_S5: "gbs::pass2d<double, 4, 5, true, 1, false, false>",
+            B.VARIANT_TEMPORAL_S6: "gbs::pass2d<double, 4, 6, true, 1, false, false>",
+            B.VARIANT_TEMPORAL_WG4: "gbs::pass2d<double, 4, 7, false, 4, false, false>",
+            B.VARIANT_TEMPORAL_WG8: "gbs::pass2d<double, 4, 7, false, 8, false, false>",
             B.VARIANT_FLAT: "gbs::lf_kernel<double, 4, 2>"}.get(variant,
                                                               "gbs::lf_march2d<double, 4, ...>")
     temporal = variant in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
