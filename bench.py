@@ -352,6 +352,21 @@ def bench_3d(args):
         log("acoustic3d forward %s: %.3f s for %d macro steps" % (dtype, res[dtype], nm))
         del pl, y
         release()
+    # the plain FP64 form: one streaming launch per sequence per leap-frog
+    # step (a few macro steps suffice: the cost per macro step is constant)
+    n_plain = min(nm, 3)
+    pl = make(torch.float64, range(R), c2)
+    pl.set_variant(B.VARIANT_PLAIN)
+    y = torch.zeros((R, 4, n, n, n), dtype=torch.float64, device=dev)
+    pl.step(y, y, n_macro=1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    pl.step(y, y, n_macro=n_plain)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t) * 1e3 / n_plain
+    log("acoustic3d plain FP64: %.1f ms per macro step" % plain_ms)
+    del pl, y
+    release()
     t32 = res[torch.float32]
     fwd_err = float((finals[torch.float32] - finals[torch.float64]).abs().max()
                     / finals[torch.float64].abs().max())
@@ -363,7 +378,10 @@ def bench_3d(args):
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload=cfg["name"], grid=[n, n, n], n_rhs=R, fd_order=8),
         fp64_ms_per_step=res[torch.float64] * 1e3 / nm,
-        fp32_max_rel_err_vs_fp64_pressure=fwd_err)
+        fp32_max_rel_err_vs_fp64_pressure=fwd_err,
+        plain_fp64_ms_per_step=plain_ms,
+        speedup_vs_plain=dict(fp64=plain_ms / (res[torch.float64] * 1e3 / nm),
+                              fp32=plain_ms / (t32 * 1e3 / nm)))
     if args.no_gradient:
         print(json.dumps(line), flush=True)
         return
