@@ -227,6 +227,8 @@ def bench_adjoint(args):
         else:
             pl.autotune(torch.zeros(pl.state_shape, dtype=dtype, device=dev), macro_steps=3)
         pl.set_sources([0], [s["idx"][0] * n + s["idx"][1]], [s["weight"]], s["f0"], s["delay"])
+        if not variant:
+            pl.autotune_adjoint(torch.randn(pl.state_shape, dtype=dtype, device=dev))
         pl.set_receivers([0] * len(rec), [int(r[0]) * n + int(r[1]) for r in rec])
         return pl
 
@@ -281,6 +283,8 @@ def bench_adjoint(args):
         plain_fp64=dict(forward_s=fpl, adjoint_s=bpl, grad_c2_rel_diff_vs_fp64=rel(gpl, g64)),
         speedup_vs_plain=dict(fp64=(fpl + bpl) / (f64 + b64), fp32=(fpl + bpl) / (f32 + b32)),
         forward_variant=tuned,
+        lanes={k: dict(forward=plans[k].lanes, adjoint=plans[k].adjoint_lanes)
+               for k in ("f64", "f32")},
     )
     print(json.dumps(rec_out), flush=True)
 

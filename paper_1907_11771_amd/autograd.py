@@ -16,7 +16,8 @@ segment can also keep the last two leap-frog levels of every sequence and
 macro step (gbs_step_keep_pairs), so that the adjoint steps do not rebuild
 them (gbs_adjoint_step_pairs): 2 k states per macro step of the segment.
 keep_pairs=None does this when that buffer takes at most a quarter of the
-free device memory, True always, False never.
+free device memory, True always, False never.  The adjoint steps from kept
+levels run on ``plan.adjoint_lanes`` streams when set (autotune_adjoint).
 """
 import torch
 
@@ -66,6 +67,9 @@ class _ReceiverTraces(torch.autograd.Function):
                     plan.step(y, y, t0=t0 + m * plan.H, n_macro=1)
                 if m < e - 1:
                     states.append(y.clone())
+            fwd_lanes = plan.lanes
+            if pairs is not None and plan.adjoint_lanes:
+                plan.set_lanes(plan.adjoint_lanes)
             for m in range(e - 1, s - 1, -1):
                 if pairs is not None:
                     plan.adjoint_step_pairs(t0 + m * plan.H, states[m - s], pairs[m - s], ybar,
@@ -73,6 +77,7 @@ class _ReceiverTraces(torch.autograd.Function):
                 else:
                     plan.adjoint_step(t0 + m * plan.H, states[m - s], ybar, trace_bar=gtr[m],
                                       grad_c2=grad)
+            plan.set_lanes(fwd_lanes)
         ctx.cps = None
         return ybar.to(ctx.y0_dtype), grad.to(ctx.c2_dtype), None, None, None, None, None
 

@@ -56,6 +56,8 @@ class GBSPlan:
         self.stream = torch.cuda.current_stream(self.device)
         self.handle = B.plan_create(self.problem, self.scheme, self.H, self.workspace.data_ptr(),
                                     self.workspace.numel(), self.stream.cuda_stream)
+        self.lanes = 1               # streams of the forward passes
+        self.adjoint_lanes = None    # streams of the adjoint passes (None: as the forward)
 
     @property
     def state_shape(self):
@@ -195,11 +197,45 @@ class GBSPlan:
         B.check(B.lib().gbs_plan_autotune(self.handle, y.data_ptr(), scratch.data_ptr(),
                                           int(macro_steps), ctypes.byref(v), ctypes.byref(b),
                                           ctypes.byref(l)))
+        self.lanes = l.value
         return v.value, b.value, l.value
 
     def set_lanes(self, lanes):
         """Streams the blocked passes of a macro step are spread over (1..4)."""
         B.check(B.lib().gbs_plan_set_lanes(self.handle, int(lanes)))
+        self.lanes = int(lanes)
+
+    def autotune_adjoint(self, y, repeats=4):
+        """Times the blocked adjoint from kept levels (adjoint_step_pairs) on
+        1, 2 and 3 lanes from the state ``y`` and keeps the fastest count in
+        ``adjoint_lanes`` (the forward's lane count is left as it was).
+        Returns it, or None when the plan's adjoint is not the blocked one."""
+        if not self.blocked_adjoint():
+            return None
+        self._check_state(y)
+        fwd = self.lanes
+        pairs = torch.empty(self.pairs_shape(1), dtype=self.dtype, device=self.device)
+        self.step_keep_pairs(y, torch.empty_like(y), pairs)
+        ybar = torch.zeros_like(y)
+        grad = (torch.zeros(self.c2_field.shape, dtype=torch.float64, device=self.device)
+                if self.c2_field is not None else None)
+        best, best_t = fwd, None
+        for lanes in (1, 2, 3):
+            self.set_lanes(lanes)
+            self.adjoint_step_pairs(0.0, y, pairs[0], ybar, grad_c2=grad)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(self.stream)
+            for _ in range(repeats):
+                self.adjoint_step_pairs(0.0, y, pairs[0], ybar, grad_c2=grad)
+            b.record(self.stream)
+            b.synchronize()
+            t = a.elapsed_time(b)
+            if best_t is None or t < best_t * 0.98:
+                best, best_t = lanes, t
+        self.set_lanes(fwd)
+        self.adjoint_lanes = best
+        return best
 
     def variant(self):
         out = ctypes.c_int32()

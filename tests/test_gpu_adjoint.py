@@ -289,13 +289,18 @@ def test_checkpointed_gradient_with_kept_pairs():
     y0 = fields.acoustic2d_pulse_modes(nx, n_modes=4, kmax=3, width=0.1, seed=8)[:, :ny, :]
     data = to_dev(np.random.default_rng(5).standard_normal((n_macro, len(rec))) * 1e-2)
     grads = []
-    for keep in (False, True):
+    for keep, adj_lanes in ((False, None), (True, None), (True, 3)):
+        plan.adjoint_lanes = adj_lanes
         y = to_dev(y0[None]).requires_grad_(True)
         c2 = plan.c2_field.clone().requires_grad_(True)
         tr = receiver_traces(plan, y, c2, n_macro, checkpoint_every=4, keep_pairs=keep)
         (0.5 * ((tr - data) ** 2).sum()).backward()
         grads.append((y.grad.clone(), c2.grad.clone()))
-    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+        assert plan.lanes == 1                        # the forward's lanes are restored
+    for g in grads[1:]:
+        assert torch.equal(grads[0][0], g[0]) and torch.equal(grads[0][1], g[1])
+    assert plan.autotune_adjoint(to_dev(y0[None])) in (1, 2, 3)
+    assert plan.lanes == 1
 
 
 def test_kept_pairs_need_the_blocked_form():
