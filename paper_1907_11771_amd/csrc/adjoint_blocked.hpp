@@ -141,13 +141,17 @@ void adj_pass2d(const AdjPassArgs<T> a) {
       // inputs: level 0 at row i; level -1 (later passes) or level 1's Y
       // (first pass) at the row level 1 updates now, i - S
       T om[6];
+      // this row's c^2: in FP32 queued at the end of the row step (its first
+      // reader is level 1, S row steps later), so that only a first pass,
+      // which scales the injected adjoint by it, waits for the load here; in
+      // FP64 holding it that long would spill (the kernel is at 256 VGPRs)
+      T c2n = a.c2c;
       {
         const int64_t e0 = (int64_t)irow * nx;
         const int64_t e1 = (int64_t)wrap_sub(irow, S, ny) * nx;
-        T c2n = a.c2c;
         if constexpr (VARC) {
           c2n = a.c2f[e0 + gx];
-          myq[kq * 64] = c2n;
+          if constexpr (sizeof(T) == 8) myq[kq * 64] = c2n;
         }
         W[0][u][0] = cur[e0];
         W[0][u][1] = cur[e0 + F1];
@@ -276,6 +280,7 @@ void adj_pass2d(const AdjPassArgs<T> a) {
           for (int q = 0; q < 6; ++q) W[e][c][q] = nw[q];
         }
       }
+      if constexpr (VARC && sizeof(T) == 4) myq[kq * 64] = c2n;
       irow = irow + 1 == ny ? 0 : irow + 1;
       kq = kq + 1 == CQ ? 0 : kq + 1;
     }

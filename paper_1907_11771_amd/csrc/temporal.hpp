@@ -225,12 +225,15 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
       // input rows: A_0 at row i, and for a later pass A_{-1} at the row
       // level 1 updates in this step
       T nxt[3], om[3];
+      T c2new = T(0);   // this row's c^2, queued at the end of the row step (its first
+                        // reader is level 1, S row steps later), so that its load
+                        // does not stall the levels evaluated now
       {
         const int64_t e0 = (int64_t)irow * nx;
         nxt[0] = cur[e0];
         nxt[1] = cur[e0 + F1];
         nxt[2] = cur[e0 + F2];
-        if constexpr (VARC) myq[kq * 64] = w.c2f[e0 + gx];
+        if constexpr (VARC) c2new = w.c2f[e0 + gx];
         if (!first) {
           const int64_t e1 = (int64_t)wrap_sub(irow, S, ny) * nx;
           om[0] = old[e1];
@@ -354,6 +357,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
 #pragma unroll
         for (int q = 0; q < 3; ++q) W[0][u][q] = nxt[q];
       }
+      if constexpr (VARC) myq[kq * 64] = c2new;
       irow = irow + 1 == ny ? 0 : irow + 1;
       kq = kq + 1 == CQ ? 0 : kq + 1;
       if constexpr (WPG > 1) __syncthreads();
