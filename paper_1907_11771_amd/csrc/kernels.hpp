@@ -249,11 +249,19 @@ __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
     vw[k] = cvz[e];
   }
   const int zend = min(z0 + TZ, nz);
+  // the plane z + R that step z needs is loaded one step ahead, so that its
+  // latency overlaps the previous step's work
+  {
+    const int64_t e = (int64_t)wrap(z0 + R, nz) * plane + pil;
+    pw[2 * R] = cp[e];
+    vw[2 * R] = cvz[e];
+  }
   for (int z = z0; z < zend; ++z) {
-    {
-      const int64_t e = (int64_t)wrap(z + R, nz) * plane + pil;
-      pw[2 * R] = cp[e];
-      vw[2 * R] = cvz[e];
+    T pnext = T(0), vnext = T(0);
+    if (z + 1 < zend) {
+      const int64_t e = (int64_t)wrap(z + 1 + R, nz) * plane + pil;
+      pnext = cp[e];
+      vnext = cvz[e];
     }
     const int64_t zoff = (int64_t)z * plane;
     const int64_t row = zoff + (int64_t)y * nx;
@@ -296,6 +304,8 @@ __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
       pw[k] = pw[k + 1];
       vw[k] = vw[k + 1];
     }
+    pw[2 * R] = pnext;
+    vw[2 * R] = vnext;
   }
 }
 
