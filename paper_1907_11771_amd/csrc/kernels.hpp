@@ -85,8 +85,10 @@ __device__ __forceinline__ T source_term(const SrcDesc* src, int nsrc, int64_t r
 template <typename T, int ORDER, int OP>
 __global__ __launch_bounds__(256) void lf_kernel(const StepArgs<T> a) {
   constexpr int F = NFields<OP>::F;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= a.g.field) return;
+  constexpr int LP = PointLanes<ORDER>::L;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = tid / LP;
+  if (idx >= a.g.field) return;          // a point's LP lanes leave together
   const SeqDesc<T>& d = a.seq[blockIdx.y];
   const int64_t rhs = blockIdx.z;
   const int64_t base = rhs * a.g.state;
@@ -94,7 +96,13 @@ __global__ __launch_bounds__(256) void lf_kernel(const StepArgs<T> a) {
   decompose(idx, a.g, x, y, z);
   const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
   T f[F];
-  eval_rhs<T, ORDER, OP>(d.cur + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
+  if constexpr (LP > 1) {
+    f[0] = -fourier_dsum_lanes<T, LP>(d.cur + base, x, a.g.nx, (const T*)a.g.fourier,
+                                      (int)(tid % LP));
+    if (tid % LP) return;
+  } else {
+    eval_rhs<T, ORDER, OP>(d.cur + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
+  }
   if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
 #pragma unroll
   for (int q = 0; q < F; ++q) {
@@ -382,7 +390,9 @@ __global__ __launch_bounds__(256) void first_march3d(const FirstArgs<T> a) {
 template <typename T, int ORDER, int OP>
 __global__ __launch_bounds__(256) void first_kernel(const FirstArgs<T> a) {
   constexpr int F = NFields<OP>::F;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int LP = PointLanes<ORDER>::L;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = tid / LP;
   if (idx >= a.g.field) return;
   const int64_t rhs = blockIdx.z;
   const int64_t base = rhs * a.g.state;
@@ -390,7 +400,13 @@ __global__ __launch_bounds__(256) void first_kernel(const FirstArgs<T> a) {
   decompose(idx, a.g, x, y, z);
   const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
   T f[F];
-  eval_rhs<T, ORDER, OP>(a.y0 + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
+  if constexpr (LP > 1) {
+    f[0] = -fourier_dsum_lanes<T, LP>(a.y0 + base, x, a.g.nx, (const T*)a.g.fourier,
+                                      (int)(tid % LP));
+    if (tid % LP) return;
+  } else {
+    eval_rhs<T, ORDER, OP>(a.y0 + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
+  }
   if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
 #pragma unroll
   for (int q = 0; q < F; ++q) {
@@ -426,7 +442,9 @@ struct RK4Args {
 template <typename T, int ORDER, int OP>
 __global__ __launch_bounds__(256) void rk4_stage(const RK4Args<T> a) {
   constexpr int F = NFields<OP>::F;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int LP = PointLanes<ORDER>::L;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = tid / LP;
   if (idx >= a.g.field) return;
   const int64_t rhs = blockIdx.z;
   const int64_t base = rhs * a.g.state;
@@ -434,7 +452,13 @@ __global__ __launch_bounds__(256) void rk4_stage(const RK4Args<T> a) {
   decompose(idx, a.g, x, y, z);
   const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
   T f[F];
-  eval_rhs<T, ORDER, OP>(a.ys + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
+  if constexpr (LP > 1) {
+    f[0] = -fourier_dsum_lanes<T, LP>(a.ys + base, x, a.g.nx, (const T*)a.g.fourier,
+                                      (int)(tid % LP));
+    if (tid % LP) return;
+  } else {
+    eval_rhs<T, ORDER, OP>(a.ys + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
+  }
   if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
 #pragma unroll
   for (int q = 0; q < F; ++q) {

@@ -637,7 +637,8 @@ void launch_lf(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gx, unsigned 
 template <typename T, int ORDER, int OP>
 int run(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   const int block = 256;
-  const unsigned gx = (unsigned)((P->field + block - 1) / block);
+  const unsigned gx =
+      (unsigned)((P->field * PointLanes<ORDER>::L + block - 1) / block);
   const unsigned gz = (unsigned)P->prob.n_rhs;
   FirstArgs<T> fa;
   StepArgs<T> sa;
@@ -710,7 +711,7 @@ int run_rk4(gbs_plan* P, double t0, int n_steps, double h, const T* yin, T* yout
   ra.acc = P->acc;
   ra.h = h;
   T* st[2] = {(T*)P->lev[0][0], (T*)P->lev[0][1]};
-  const unsigned gx = (unsigned)((P->field + 255) / 256);
+  const unsigned gx = (unsigned)((P->field * PointLanes<ORDER>::L + 255) / 256);
   const unsigned gz = (unsigned)P->prob.n_rhs;
   const double frac[4] = {0.0, 0.5, 0.5, 1.0};
   for (int m = 0; m < n_steps; ++m) {

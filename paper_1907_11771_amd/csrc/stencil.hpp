@@ -101,6 +101,41 @@ __device__ __forceinline__ T fourier_dsum(const T* __restrict__ u, int i, int n,
   return sum;
 }
 
+// The same sum split over L consecutive lanes (L a power of two dividing 64):
+// lane `sub` of the point takes k = 1 + sub, 1 + sub + L, ... with its own
+// compensated sum, and a butterfly over the L lanes adds the partial sums
+// and their compensations (every lane ends with the same value: each
+// pairwise addition is commutative).  The point's L lanes must all be
+// active.
+template <typename T, int L>
+__device__ __forceinline__ T fourier_dsum_lanes(const T* __restrict__ u, int i, int n,
+                                                const T* __restrict__ b, int sub) {
+  const int K = (n - 1) / 2;
+  T sum = T(0), comp = T(0);
+#pragma unroll 4
+  for (int k = 1 + sub; k <= K; k += L) {
+    const int up = i + k < n ? i + k : i + k - n;
+    const int dn = i - k >= 0 ? i - k : i - k + n;
+    const T y = b[k - 1] * (u[up] - u[dn]) - comp;
+    const T t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+  }
+#pragma unroll
+  for (int off = 1; off < L; off <<= 1) {
+    sum += __shfl_xor(sum, off);
+    comp += __shfl_xor(comp, off);
+  }
+  return sum - comp;
+}
+
+// Lanes per grid point of the streaming kernels: the Fourier derivative's
+// long sum is split over 8 lanes, the finite differences use one.
+template <int ORDER>
+struct PointLanes {
+  static constexpr int L = ORDER == GBS_FD_SPECTRAL ? 8 : 1;
+};
+
 // Mode bits of one sequence in one leap-frog launch.
 enum : int32_t {
   MODE_LAST = 1,    // s == N_j: average, combine, no level written
