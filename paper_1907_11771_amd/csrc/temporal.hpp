@@ -484,8 +484,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void combine_kernel(const CombineArgs<T> a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  double v = a.c[0] * a.ystar[0][i];
-  for (int j = 1; j < a.k; ++j) v = v + a.c[j] * a.ystar[j][i];
+  // each y* is read once: non-temporal loads keep them from displacing
+  // y_out, which the next macro step's first passes read
+  double v = a.c[0] * __builtin_nontemporal_load(a.ystar[0] + i);
+  for (int j = 1; j < a.k; ++j) v = v + a.c[j] * __builtin_nontemporal_load(a.ystar[j] + i);
   a.yout[i] = (T)v;
 }
 
@@ -514,8 +516,8 @@ __global__ __launch_bounds__(256) void combine_batch(const CombineItem<T>* items
   const CombineItem<T>* it = items + lo;
   const int64_t i = (int64_t)(b - it->block_begin) * blockDim.x + threadIdx.x;
   if (i >= it->n) return;
-  double v = it->c[0] * it->ystar[0][i];
-  for (int j = 1; j < it->k; ++j) v = v + it->c[j] * it->ystar[j][i];
+  double v = it->c[0] * __builtin_nontemporal_load(it->ystar[0] + i);
+  for (int j = 1; j < it->k; ++j) v = v + it->c[j] * __builtin_nontemporal_load(it->ystar[j] + i);
   it->yout[i] = (T)v;
 }
 
