@@ -326,15 +326,16 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
             if (!final_) {
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                w.out_a[pt + q * F1] = In[c][q];
-                w.out_b[pt + q * F1] = nw[q];
+                __builtin_nontemporal_store(In[c][q], w.out_a + pt + q * F1);
+                __builtin_nontemporal_store(nw[q], w.out_b + pt + q * F1);
               }
             } else {
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
                 const T ym1 = (e >= 2) ? W[e >= 2 ? e - 2 : 0][c][q] : (first ? In[c][q] : om[q]);
-                w.ystar[pt + q * F1] =
-                    0.25 * (((double)ym1 + 2.0 * (double)In[c][q]) + (double)nw[q]);
+                __builtin_nontemporal_store(
+                    0.25 * (((double)ym1 + 2.0 * (double)In[c][q]) + (double)nw[q]),
+                    w.ystar + pt + q * F1);
                 if (keep) {
                   w.out_a[pt + q * F1] = ym1;
                   w.out_b[pt + q * F1] = In[c][q];
