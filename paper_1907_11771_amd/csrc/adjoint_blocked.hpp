@@ -253,10 +253,11 @@ void adj_pass2d(const AdjPassArgs<T> a) {
             if (!final_) {
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                d.out_a[base + pt + q * F1] = In[c][q];
-                d.out_a[base + ST + pt + q * F1] = In[c][3 + q];
-                d.out_b[base + pt + q * F1] = nw[q];
-                d.out_b[base + ST + pt + q * F1] = nw[3 + q];
+                // read back only by the next round's launch
+                __builtin_nontemporal_store(In[c][q], d.out_a + base + pt + q * F1);
+                __builtin_nontemporal_store(In[c][3 + q], d.out_a + base + ST + pt + q * F1);
+                __builtin_nontemporal_store(nw[q], d.out_b + base + pt + q * F1);
+                __builtin_nontemporal_store(nw[3 + q], d.out_b + base + ST + pt + q * F1);
               }
             } else {
               // lambda_1 = level g (Z_{N-1}), lambda_0 = level g-1 (Z_{N-2})
