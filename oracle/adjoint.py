@@ -21,7 +21,10 @@ a * l_p ⊙ (-div v_n), with l_p the pressure part of the adjoint of the
 level that the application produced.
 
 Misfit (receiver residuals at macro-step ends n = 1..n_macro):
-  L = 1/2 sum_n sum_r (p_n(x_r) - d_{n,r})^2.
+  L = 1/2 sum_n sum_r (p_n(x_r) - d_{n,r})^2,
+with x_r a grid point of the pressure field in any dimension; a run of
+several independent right-hand sides (sharing c^2) sums L and dL/dc^2 over
+them (misfit_gradient_rhs).
 """
 import numpy as np
 
@@ -62,15 +65,24 @@ def macro_step_adjoint(op, t0, y0, H, steps, c, ybar_out, want_c2=True):
     return ybar0, g
 
 
+def _at(receivers):
+    """Index tuple of the receivers' grid points: receivers is an (R, d) array
+    whose rows are grid indices in array order ((iy, ix) or (iz, iy, ix))."""
+    receivers = np.asarray(receivers, dtype=np.int64)
+    return tuple(receivers[:, k] for k in range(receivers.shape[1]))
+
+
 def misfit(op, t0, y0, H, steps, c, n_macro, receivers, data):
     """Forward run; returns (L, states) with states[n] = y after n macro steps
-    (states[0] = y0).  receivers: (R, 2) array of (iy, ix); data: (n_macro, R)."""
+    (states[0] = y0).  receivers: (R, d) grid indices of the pressure field;
+    data: (n_macro, R)."""
     from .gbs import macro_step
+    at = _at(receivers)
     ys = [np.asarray(y0, dtype=np.float64)]
     L = 0.0
     for n in range(1, n_macro + 1):
         ys.append(macro_step(op, t0 + (n - 1) * H, ys[-1], H, steps, c))
-        res = ys[-1][0][receivers[:, 0], receivers[:, 1]] - data[n - 1]
+        res = ys[-1][0][at] - data[n - 1]
         L += 0.5 * float(np.sum(res * res))
     return L, ys
 
@@ -79,11 +91,26 @@ def misfit_gradient(op, t0, y0, H, steps, c, n_macro, receivers, data):
     """Returns (L, dL/dy0, dL/dc2) by the reverse sweep over stored macro-step
     boundary states."""
     L, ys = misfit(op, t0, y0, H, steps, c, n_macro, receivers, data)
+    at = _at(receivers)
     ybar = np.zeros_like(ys[0])
     g = np.zeros(op.shape)
     for n in range(n_macro, 0, -1):
-        res = ys[n][0][receivers[:, 0], receivers[:, 1]] - data[n - 1]
-        np.add.at(ybar[0], (receivers[:, 0], receivers[:, 1]), res)
+        res = ys[n][0][at] - data[n - 1]
+        np.add.at(ybar[0], at, res)
         ybar, gn = macro_step_adjoint(op, t0 + (n - 1) * H, ys[n - 1], H, steps, c, ybar)
         g += gn
     return L, ybar, g
+
+
+def misfit_gradient_rhs(ops, t0, y0s, H, steps, c, n_macro, receivers, data):
+    """Several independent right-hand sides r (each its own operator ops[r],
+    i.e. its own sources, all with the same c^2; initial state y0s[r];
+    receivers[r], data[r] as in misfit_gradient).  Returns
+    (sum_r L_r, [dL/dy0_r], sum_r dL_r/dc2)."""
+    L, gys, g = 0.0, [], None
+    for op, y0, rec, d in zip(ops, y0s, receivers, data):
+        Lr, gy, gc = misfit_gradient(op, t0, y0, H, steps, c, n_macro, rec, d)
+        L += Lr
+        gys.append(gy)
+        g = gc if g is None else g + gc
+    return L, gys, g

@@ -82,3 +82,25 @@ def test_acoustic_plane_wave_dispersion():
     assert np.max(np.abs(f[0] - want)) < 2e-3 * 2 * np.pi * k
     assert np.max(np.abs(f[1] - want)) < 2e-3 * 2 * np.pi * k
     assert np.max(np.abs(f[2])) == 0.0
+
+
+@pytest.mark.parametrize("f0,delay", [(25.0, 0.06), (3.0, 0.5)])
+def test_ricker_amplitude_closed_form_points(f0, delay):
+    # the Ricker wavelet r(tau) = (1 - 2 pi^2 f0^2 tau^2) exp(-pi^2 f0^2 tau^2),
+    # tau = t - delay: r = 1 at the delay, zeros at tau = +-1/(sqrt 2 pi f0),
+    # minima -2 exp(-3/2) at tau = +-sqrt(3/2)/(pi f0), even in tau, and
+    # decaying to 0 (a factor of 2 in either exponent, a wrong sign or a
+    # shifted delay moves one of these points)
+    s = OP.Source((0, 0), f0, delay, 1.0)
+    assert s.amplitude(delay) == 1.0
+    tz = 1.0 / (np.sqrt(2.0) * np.pi * f0)
+    tm = np.sqrt(1.5) / (np.pi * f0)
+    for sign in (1.0, -1.0):
+        assert abs(s.amplitude(delay + sign * tz)) <= 1e-14
+        assert s.amplitude(delay + sign * tm) == pytest.approx(-2.0 * np.exp(-1.5), rel=1e-14)
+        # a minimum: neighbours on both sides are larger
+        for d in (1e-4, -1e-4):
+            assert s.amplitude(delay + sign * tm * (1 + d)) > s.amplitude(delay + sign * tm)
+    taus = np.linspace(0.0, 3.0 * tm, 50)
+    assert np.allclose(s.amplitude(delay + taus), s.amplitude(delay - taus), rtol=0, atol=1e-12)
+    assert abs(s.amplitude(delay + 6.0 / f0)) < 1e-100
