@@ -2,11 +2,14 @@
 (2048^2 periodic grid, FP64, FD4, order-8 scheme over N = 2,4,...,12) on one
 MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint]
 
 One "step" is one macro step: all six GBS sequences (forward Euler, N_j
 leap-frog steps, averaging) and the FP64 weighted combination, i.e.
-1 + sum N_j = 43 RHS evaluations per grid point.  Prints one JSON line.
+1 + sum N_j = 43 RHS evaluations per grid point.  Prints one JSON line; its
+"fwd_adj" object is the metric's second half, forward + adjoint time at
+fixed error against the plain form (the 1024^2 differentiation workload,
+400 macro steps), with the adjoint pass kernel's roofline.
 """
 import argparse
 import json
@@ -19,12 +22,109 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 STREAM_BYTES_PER_UPDATE = 72.0   # FP64 2-D acoustic leap-frog update, streaming: 3 F b
-# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
-# the plain-copy calibration) for the kernel as it is now; see profiles/.  An
-# entry must be removed when its kernel changes.
-MEASURED_TRAFFIC_BYTES_PER_LAUNCH = {
-    "gbs::pass2d<double, 4, 5, true, 1, false, false>": 1.476e9,    # profiles/pass2d_acoustic2d_2048_fd4_f64.txt
-}
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1907_11771_amd", "csrc")
+
+
+def source_sha():
+    """Fingerprint of the library's device and launch code (every file under
+    csrc/): a counter profile applies only to the code it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of ``kernel`` on ``workload`` from the counter
+    summaries under profiles/ (lines "TRAFFIC {json}" written by
+    --summarize-counters), or None when no summary was taken on the current
+    sources for exactly that kernel and workload."""
+    sha = source_sha()
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".txt"):
+            continue
+        with open(os.path.join(PROFILES, name)) as fh:
+            for ln in fh:
+                if not ln.startswith("TRAFFIC "):
+                    continue
+                rec = json.loads(ln[len("TRAFFIC "):])
+                if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                        and rec.get("source_sha") == sha):
+                    rec["profile"] = "profiles/" + name
+                    return rec
+    return None
+
+
+def kernel_base_name(k):
+    """'void gbs::pass2d<double, 4, 5, ...>(gbs::PassArgs<double>)' ->
+    'gbs::pass2d<double, 4, 5, ...>' (the profiler's name without the return
+    type and the parameter list)."""
+    k = k.strip()
+    if k.startswith("void "):
+        k = k[5:]
+    depth = 0
+    for i, ch in enumerate(k):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return k[:i].strip()
+    return k
+
+
+def _counter_rows(path):
+    """(kernel name, dispatch id, counter, value) rows of a rocprofv3
+    counter_collection CSV."""
+    import csv
+    rows = []
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            rows.append((r["Kernel_Name"], int(r["Dispatch_Id"]), r["Counter_Name"],
+                         float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_counters(args):
+    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) of a kernel and the same two counters on the plain 1 GiB copy
+    (--copy-calibration) into HBM bytes per launch, scaled so that the copy
+    reads and writes exactly 1 GiB; prints the TRAFFIC line a profile
+    summary carries (bench.py's roofline 'traffic' reads it back)."""
+    fetch, write, cfetch, cwrite = args.summarize_counters
+
+    def per_dispatch(path, counter, match):
+        vals = {}
+        for k, d, c, v in _counter_rows(path):
+            if c == counter and match(k):
+                vals[d] = vals.get(d, 0.0) + v
+        return [vals[d] for d in sorted(vals)]
+
+    is_kernel = lambda k: kernel_base_name(k) == args.kernel
+    is_copy = lambda k: "copy" in k.lower() or "elementwise" in k.lower()
+    f = per_dispatch(fetch, "FETCH_SIZE", is_kernel)
+    w = per_dispatch(write, "WRITE_SIZE", is_kernel)
+    cf = per_dispatch(cfetch, "FETCH_SIZE", is_copy)
+    cw = per_dispatch(cwrite, "WRITE_SIZE", is_copy)
+    if not (f and w and cf and cw):
+        raise SystemExit("no dispatches of %r (or of the copy) in the counter files" % args.kernel)
+    gib = float(1 << 30)
+    sf = gib / (max(cf) * 1024.0)      # bytes per counted KiB, from the copy
+    sw = gib / (max(cw) * 1024.0)
+    fb = sum(f) / len(f) * 1024.0 * sf
+    wb = sum(w) / len(w) * 1024.0 * sw
+    rec = dict(kernel=args.kernel, workload=args.counters_workload, source_sha=source_sha(),
+               launches=len(f), fetch_scale=sf, write_scale=sw,
+               fetch_bytes_per_launch=fb, write_bytes_per_launch=wb,
+               bytes_per_launch=fb + wb,
+               fetch_bytes_by_launch=[x * 1024.0 * sf for x in f],
+               write_bytes_by_launch=[x * 1024.0 * sw for x in w])
+    print("TRAFFIC " + json.dumps(rec))
 
 
 def kernel_names(variant, B):
@@ -196,10 +296,19 @@ def bench_batch(args):
 
 
 def bench_adjoint(args):
+    """The forward + adjoint workload on its own line (adjoint_leg)."""
+    nm = None if args.steps == 500 else args.steps
+    rec = adjoint_leg(nm)
+    print(json.dumps(rec), flush=True)
+
+
+def adjoint_leg(n_macro=None):
     """Forward + checkpointed adjoint of the receiver misfit (gradients with
     respect to c^2 and p(0)) on the 1024^2 workload: FP64 blocked forward,
     FP32 stepping, and the plain FP64 form; the FP32 gradient's error is
-    stated against the FP64 one."""
+    stated against the FP64 one.  Also the blocked adjoint pass kernel's
+    roofline: its algorithmic bytes over its HIP-event time in one more
+    FP64 backward pass on one lane."""
     import numpy as np
     import torch
     from paper_1907_11771_amd import binding as B
@@ -208,7 +317,7 @@ def bench_adjoint(args):
     from synth import fields, workloads
 
     cfg = workloads.CONFIG_ADJOINT
-    n, nm = cfg["n"], cfg["n_macro"] if args.steps == 500 else args.steps
+    n, nm = cfg["n"], cfg["n_macro"] if n_macro is None else n_macro
     steps, w, _ = scheme_weights(cfg["scheme"])
     dev = torch.device("cuda:0")
     cs = fields.lognormal_speed((n, n), seed=cfg["speed_seed"])
@@ -270,6 +379,26 @@ def bench_adjoint(args):
     fpl, bpl, gpl, _ = run(plans["plain"], torch.float64)
     tuned = {k: plans[k].variant() for k in ("f64", "f32")}
     rel = lambda a, b: float((a - b).norm() / b.norm())
+    # the adjoint pass kernel alone: one more FP64 backward on one lane with
+    # every pass launch bracketed by HIP events
+    p64 = plans["f64"]
+    lanes64 = p64.adjoint_lanes
+    p64.adjoint_lanes = 1
+    y0 = torch.zeros((1, 3, n, n), dtype=torch.float64, device=dev, requires_grad=True)
+    c2v = torch.from_numpy(c2).to(dev).requires_grad_(True)
+    tr = receiver_traces(p64, y0, c2v, nm, checkpoint_every=cfg["checkpoint_every"])
+    loss = 0.5 * ((tr - data) ** 2).sum()
+    torch.cuda.synchronize()
+    p64.set_timing(1)
+    loss.backward()
+    torch.cuda.synchronize()
+    adj_ms, adj_n, adj_bytes = p64.get_adjoint_timing()
+    p64.set_timing(0)
+    p64.adjoint_lanes = lanes64
+    adj_kernel = "gbs::adj_pass2d<double, 3, true>"
+    prof = measured_traffic(adj_kernel, cfg["name"])
+    adj_launch_s = adj_ms * 1e-3 / max(adj_n, 1)
+    achieved = adj_bytes / max(adj_n, 1) / adj_launch_s / 1e9 if adj_n else None
     upd = n * n * (1 + sum(steps)) * nm
     rec_out = dict(
         metric="fwd+adjoint time at fixed error vs plain", value=(f64 + b64), unit="s",
@@ -285,8 +414,16 @@ def bench_adjoint(args):
         forward_variant=tuned,
         lanes={k: dict(forward=plans[k].lanes, adjoint=plans[k].adjoint_lanes)
                for k in ("f64", "f32")},
+        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=achieved / HBM_PEAK_GBS if achieved else None,
+                      traffic=prof["bytes_per_launch"] / adj_launch_s / 1e9 if prof else None,
+                      traffic_bytes_per_launch=prof["bytes_per_launch"] if prof else None,
+                      traffic_profile=prof["profile"] if prof else None,
+                      kernel=adj_kernel, avg_launch_us=adj_launch_s * 1e6, launches=adj_n,
+                      algorithmic_bytes_per_launch=adj_bytes / max(adj_n, 1),
+                      lanes=1),
     )
-    print(json.dumps(rec_out), flush=True)
+    return rec_out
 
 
 def bench_3d(args):
@@ -586,10 +723,19 @@ def main():
                     help="stepping precision of the batch workload")
     ap.add_argument("--no-gradient", action="store_true",
                     help="acoustic3d: the forward runs only")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="leave out the forward + adjoint leg of the default line")
+    ap.add_argument("--summarize-counters", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="print the TRAFFIC line of --kernel from rocprofv3 counter files")
+    ap.add_argument("--kernel", help="kernel name for --summarize-counters")
+    ap.add_argument("--counters-workload", help="workload name for --summarize-counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(args)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method's data-parallel path is "
               "benchmarked on a single MI355X (--gpus 1)", file=sys.stderr)
@@ -669,7 +815,8 @@ def main():
     step_bytes = sb * args.steps
     achieved = step_bytes / (step_ms * 1e-3) / 1e9
     launch_s = step_ms * 1e-3 / max(step_n, 1)
-    measured = MEASURED_TRAFFIC_BYTES_PER_LAUNCH.get(kstep)
+    prof = measured_traffic(kstep, cfg["name"])
+    measured = prof["bytes_per_launch"] if prof else None
     traffic = measured / launch_s / 1e9 if measured else None
     rec = dict(
         metric="grid-pt RHS updates/s",
@@ -686,7 +833,8 @@ def main():
                     else None),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                      traffic_bytes_per_launch=measured, kernel=kstep,
+                      traffic_bytes_per_launch=measured,
+                      traffic_profile=prof["profile"] if prof else None, kernel=kstep,
                       avg_launch_us=step_ms * 1e3 / max(step_n, 1), launches=step_n,
                       algorithmic_bytes_per_launch=step_bytes / max(step_n, 1)),
         # the streaming form must move 72 B per update; this is the rate those
@@ -698,6 +846,13 @@ def main():
         aux_kernel=dict(kernel=kaux, avg_launch_us=aux_ms * 1e3 / max(aux_n, 1),
                         gbps=ab * args.steps / (aux_ms * 1e-3) / 1e9 if aux_ms else None),
     )
+    del plan, y, out
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        # the metric's second half: forward + adjoint time at fixed error
+        # against the plain form, with the adjoint pass kernel's roofline
+        rec["fwd_adj"] = adjoint_leg()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(cfg, y0)
     print(json.dumps(rec), flush=True)

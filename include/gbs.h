@@ -12,7 +12,11 @@
  * (Sect. 3.2) with weights c that satisfy the order constraints of eq.
  * (vander) and, when k > p/2, free weights chosen for the stability domain
  * (Sect. 3.7, eqs. order_constraints and cdep_computation).  f(t_0, y_0) is
- * the same for every sequence and is evaluated once (Sect. 3.6).
+ * the same for every sequence (Sect. 3.6): the streaming variants evaluate
+ * it once per macro step and share it; the temporally blocked variants
+ * evaluate it again in each sequence's first pass, which Sect. 3.6 allows
+ * (they count 1 + sum_j N_j evaluations per point like the others, but
+ * perform k + sum_j N_j).
  *
  * Conventions for every entry point:
  *  - Return value: GBS_OK (0) or a negative status; gbs_last_error() then
@@ -161,6 +165,16 @@ int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gbs_scheme* s
                     double H, void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /*
+ * gbs_plan_set_stream — enqueue the plan's later work on another
+ * hipStream_t (NULL: the null stream).  The new stream first waits for the
+ * work already enqueued on the old one (an event), so the plan's workspace
+ * is never used by two streams at once; the caller orders its own buffers.
+ * Errors: GBS_EINVAL (null plan), GBS_EDEVICE (event calls failed; the plan
+ * keeps the old stream).
+ */
+int gbs_plan_set_stream(gbs_plan* plan, void* hip_stream);
+
+/*
  * gbs_plan_set_sources — point sources on the pressure equation of an
  * acoustic plan: f_p[rhs[s]][flat_index[s]] += weight[s] * r(t), with the
  * Ricker wavelet r(t) = (1 - 2 a) exp(-a), a = (pi f0 (t - delay))^2,
@@ -292,10 +306,25 @@ int gbs_plan_get_timing(gbs_plan* plan, double* step_ms, int64_t* step_launches,
                         double* aux_ms, int64_t* aux_launches);
 
 /*
+ * gbs_plan_get_adjoint_timing — with timing enabled, the summed duration
+ * (ms) and the count of the temporally blocked adjoint's pass launches
+ * (adj_pass2d; timed when the plan runs on one lane) since the last read,
+ * and their algorithmic HBM bytes: per launch, y_N, y_{N-1} and ybar read by
+ * a first pass or the two Z levels (Y and Psi) by a later one, the two Z
+ * levels written (or lambda_0 + lambda_1 and h lambda_1 in FP64 by a final
+ * pass), the FP64 gradient row sums written or updated, and c^2 once.  The
+ * read synchronises the plan's stream and resets.  Outputs are nullable.
+ */
+int gbs_plan_get_adjoint_timing(gbs_plan* plan, double* pass_ms, int64_t* pass_launches,
+                                double* pass_bytes);
+
+/*
  * gbs_plan_algorithmic_bytes — HBM bytes one macro step must move with the
  * plan's current variant, per kernel class (stepping kernel / auxiliary
  * kernel, as in gbs_plan_get_timing), and the launches of each per macro
- * step: every level, y*, accumulator or state each kernel reads or writes
+ * step: every state a launch reads counted once per launch (y0, shared by
+ * the first passes of all sequences, and the c^2 field, shared by all
+ * sequences and right-hand sides), every level, y* or accumulator it writes
  * once over the grid; halo re-reads and redundant edge work are not
  * counted.  For measurement only.
  */
@@ -409,6 +438,8 @@ int gbs_batch_plan_create(gbs_batch_plan** out, int32_t n_inst, const gbs_proble
                           size_t workspace_bytes, void* hip_stream);
 int gbs_batch_set_variant(gbs_batch_plan* plan, int32_t variant, int32_t band);
 int gbs_batch_set_graph(gbs_batch_plan* plan, int32_t enabled);
+/* gbs_batch_set_stream — as gbs_plan_set_stream, for a batch plan. */
+int gbs_batch_set_stream(gbs_batch_plan* plan, void* hip_stream);
 int gbs_batch_step(gbs_batch_plan* plan, int32_t n_macro, void* const* y);
 int gbs_batch_autotune(gbs_batch_plan* plan, void* const* y, int32_t macro_steps,
                        int32_t* variant_out, int32_t* band_out);

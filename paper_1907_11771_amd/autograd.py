@@ -18,6 +18,12 @@ them (gbs_adjoint_step_pairs): 2 k states per macro step of the segment.
 keep_pairs=None does this when that buffer takes at most a quarter of the
 free device memory, True always, False never.  The adjoint steps from kept
 levels run on ``plan.adjoint_lanes`` streams when set (autotune_adjoint).
+
+The plan's coefficient field is shared by all calls on the plan: each
+forward copies its c^2 into it and keeps a copy, and each backward puts that
+copy back first, so forwards of other c^2 between a forward and its backward
+(a line search, a sum of losses) do not change the gradient.  After a
+backward the field holds that backward's c^2.
 """
 import torch
 
@@ -43,12 +49,16 @@ class _ReceiverTraces(torch.autograd.Function):
         ctx.plan, ctx.n_macro, ctx.t0, ctx.ck = plan, n_macro, t0, checkpoint_every
         ctx.keep_pairs = keep_pairs
         ctx.cps = cps
+        # the plan's field is shared by every call on the plan: keep this
+        # forward's c^2, which the backward pass puts back before recomputing
+        ctx.c2_fwd = plan.c2_field.clone()
         ctx.y0_dtype, ctx.c2_dtype = y0.dtype, c2.dtype
         return traces[:, :getattr(plan, "n_rec", 0)].to(y0.dtype)
 
     @staticmethod
     def backward(ctx, gtr):
         plan, n, t0, ck = ctx.plan, ctx.n_macro, ctx.t0, ctx.ck
+        plan.c2_field.copy_(ctx.c2_fwd)
         gtr = gtr.to(plan.dtype).contiguous()
         ybar = torch.zeros_like(ctx.cps[0])
         grad = torch.zeros(plan.c2_field.shape, dtype=torch.float64, device=plan.device)
@@ -79,6 +89,7 @@ class _ReceiverTraces(torch.autograd.Function):
                                       grad_c2=grad)
             plan.set_lanes(fwd_lanes)
         ctx.cps = None
+        ctx.c2_fwd = None
         return ybar.to(ctx.y0_dtype), grad.to(ctx.c2_dtype), None, None, None, None, None
 
 

@@ -82,7 +82,9 @@ def lib():
             "gbs_plan_autotune": [vp, vp, vp, i32, P(i32), P(i32), P(i32)],
             "gbs_plan_set_lanes": [vp, i32],
             "gbs_plan_set_band": [vp, i32],
+            "gbs_plan_set_stream": [vp, vp],
             "gbs_plan_get_timing": [vp, P(dbl), P(i64), P(dbl), P(i64)],
+            "gbs_plan_get_adjoint_timing": [vp, P(dbl), P(i64), P(dbl)],
             "gbs_plan_updates_per_macro_step": [vp, P(dbl)],
             "gbs_plan_algorithmic_bytes": [vp, P(dbl), P(i64), P(dbl), P(i64)],
             "gbs_plan_destroy": [vp],
@@ -96,6 +98,7 @@ def lib():
             "gbs_batch_plan_create": [P(vp), i32, P(Problem), P(Scheme), P(dbl), vp, sz, vp],
             "gbs_batch_set_variant": [vp, i32, i32],
             "gbs_batch_set_graph": [vp, i32],
+            "gbs_batch_set_stream": [vp, vp],
             "gbs_batch_step": [vp, i32, P(vp)],
             "gbs_batch_autotune": [vp, P(vp), i32, P(i32), P(i32)],
             "gbs_batch_updates_per_macro_step": [vp, P(dbl)],

@@ -20,7 +20,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -100,6 +103,11 @@ struct gbs_plan {
   bool timing = false;
   std::vector<EventPair> lf_ev, first_ev;
   size_t lf_used = 0, first_used = 0;
+  // timing of the blocked adjoint's pass launches (one lane), with the
+  // algorithmic bytes of the timed launches
+  std::vector<EventPair> adj_ev;
+  size_t adj_used = 0;
+  double adj_bytes = 0;
 };
 
 namespace {
@@ -402,16 +410,28 @@ int make_schedule(const int32_t* steps, int k, int G, int R, int wpg, PassSchedu
   return GBS_OK;
 }
 
-// Wavefronts the GPU holds at once for a pass kernel (occupancy x CUs).
+// Wavefronts the current device holds at once for a pass kernel (occupancy
+// x CUs), queried once per (device, kernel, block size).
 template <typename K>
 int resident_waves(K kernel, int block) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, int>, int> cache;
   int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_tuple(dev, (const void*)kernel, block);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
       per_cu < 1 || cus < 1)
     return 0;
-  return per_cu * cus * (block / 64);
+  const int waves = per_cu * cus * (block / 64);
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = waves;
+  return waves;
 }
 
 // Rows per band of one round of passes when the plan leaves it automatic
@@ -453,9 +473,9 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   pa.src_dev = P->src_dev;
   const int nx = (int)P->prob.n[0];
   constexpr int S = SKEW1 ? R + 1 : R;
-  static const int slots_c = resident_waves(pass2d<T, ORDER, G, SKEW1, WPG, false>,
+  const int slots_c = resident_waves(pass2d<T, ORDER, G, SKEW1, WPG, false>,
                                             WPG > 1 ? 64 * WPG : 256);
-  static const int slots_v = resident_waves(pass2d<T, ORDER, G, SKEW1, WPG, true>,
+  const int slots_v = resident_waves(pass2d<T, ORDER, G, SKEW1, WPG, true>,
                                             WPG > 1 ? 64 * WPG : 256);
   const int slots = (P->prob.c2_field ? slots_v : slots_c) / WPG;   // units of WPG wavefronts
   CombineArgs<T> ca;
@@ -966,6 +986,29 @@ extern "C" int gbs_plan_set_lanes(gbs_plan* P, int32_t lanes) {
   return GBS_OK;
 }
 
+namespace {
+
+// Rebind a plan to another caller stream: work enqueued from now on goes to
+// `to`, which first waits for everything already enqueued on `from`.
+int rebind_stream(hipStream_t& cur, hipStream_t to) {
+  if (to == cur) return GBS_OK;
+  hipEvent_t e;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+    return fail(GBS_EDEVICE, "creating an event failed");
+  const bool ok = hipEventRecord(e, cur) == hipSuccess && hipStreamWaitEvent(to, e, 0) == hipSuccess;
+  hipEventDestroy(e);
+  if (!ok) return fail(GBS_EDEVICE, "ordering the new stream after the old one failed");
+  cur = to;
+  return GBS_OK;
+}
+
+}  // namespace
+
+extern "C" int gbs_plan_set_stream(gbs_plan* P, void* hip_stream) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  return rebind_stream(P->stream, (hipStream_t)hip_stream);
+}
+
 extern "C" int gbs_plan_get_variant(const gbs_plan* P, int32_t* variant) {
   if (!P || !variant) return fail(GBS_EINVAL, "null argument");
   *variant = resolve_variant(P);
@@ -1040,7 +1083,8 @@ extern "C" int gbs_plan_set_timing(gbs_plan* P, int32_t enabled) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
   if (enabled < 0) return fail(GBS_EINVAL, "enabled must be >= 0");
   P->timing = enabled != 0;
-  P->lf_used = P->first_used = 0;
+  P->lf_used = P->first_used = P->adj_used = 0;
+  P->adj_bytes = 0;
   // create the events for `enabled` macro steps up front, so that timed runs
   // do not create events between launches
   if (enabled > 1) {
@@ -1049,6 +1093,23 @@ extern "C" int gbs_plan_set_timing(gbs_plan* P, int32_t enabled) {
     while (P->first_ev.size() < fi) next_event(P->first_ev, P->first_used);
     P->lf_used = P->first_used = 0;
   }
+  return GBS_OK;
+}
+
+extern "C" int gbs_plan_get_adjoint_timing(gbs_plan* P, double* pass_ms, int64_t* pass_n,
+                                           double* pass_bytes) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(GBS_EDEVICE, "stream sync failed");
+  double tot = 0;
+  for (size_t i = 0; i < P->adj_used; ++i) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, P->adj_ev[i].a, P->adj_ev[i].b) == hipSuccess) tot += ms;
+  }
+  if (pass_ms) *pass_ms = tot;
+  if (pass_n) *pass_n = (int64_t)P->adj_used;
+  if (pass_bytes) *pass_bytes = P->adj_bytes;
+  P->adj_used = 0;
+  P->adj_bytes = 0;
   return GBS_OK;
 }
 
@@ -1073,8 +1134,10 @@ extern "C" int gbs_plan_get_timing(gbs_plan* P, double* lf_ms, int64_t* lf_n, do
 }
 
 // Algorithmic HBM bytes of one macro step, per kernel class, for the variant
-// in use: every level or accumulator a kernel must read or write once over
-// the grid (halo re-reads and redundant edge work are not counted).
+// in use: every state a launch reads is counted once per launch (y0, which
+// the first passes of all sequences share, and the c^2 field, which every
+// sequence and right-hand side shares), every level, y* or accumulator it
+// writes once; halo re-reads and redundant edge work are not counted.
 extern "C" int gbs_plan_algorithmic_bytes(const gbs_plan* P, double* step_bytes,
                                           int64_t* step_launches, double* aux_bytes,
                                           int64_t* aux_launches) {
@@ -1082,6 +1145,8 @@ extern "C" int gbs_plan_algorithmic_bytes(const gbs_plan* P, double* step_bytes,
   const double pts = (double)P->field * P->prob.n_rhs;
   const double Fb = (double)P->F * dsize(P->prob.dtype);   // one level, per point
   const double F8 = (double)P->F * 8.0;                     // one FP64 state, per point
+  // the coefficient field, read once per launch (shared by the right-hand sides)
+  const double c2b = P->prob.c2_field ? (double)P->field * dsize(P->prob.dtype) : 0.0;
   const int v = resolve_variant(P);
   double sb = 0, ab = 0;
   int64_t sl = 0, al = 0;
@@ -1092,11 +1157,12 @@ extern "C" int gbs_plan_algorithmic_bytes(const gbs_plan* P, double* step_bytes,
       const int E = P->steps[j] + 1, np = (E + Gx - 1) / Gx;
       maxpass = std::max(maxpass, np);
       for (int q = 0; q < np; ++q) {
-        sb += (q == 0 ? Fb : 2 * Fb) * pts;                  // inputs
-        sb += (q == np - 1 ? F8 : 2 * Fb) * pts;             // outputs
+        if (q > 0) sb += 2 * Fb * pts;                       // the pair of levels in
+        sb += (q == np - 1 ? F8 : 2 * Fb) * pts;             // the pair out, or y*
       }
     }
     sl = maxpass;
+    sb += Fb * pts + sl * c2b;                               // y0 (round 0), c^2 per launch
     ab = ((double)P->k * F8 + Fb) * pts;                     // combine
     al = 1;
   } else {
@@ -1110,7 +1176,8 @@ extern "C" int gbs_plan_algorithmic_bytes(const gbs_plan* P, double* step_bytes,
       sb += last * pts;
     }
     sl = P->nmax;
-    ab = (1 + P->k) * Fb * pts;                              // first evaluation
+    sb += sl * c2b;
+    ab = (1 + P->k) * Fb * pts + c2b;                        // first evaluation
     al = 1;
   }
   if (step_bytes) *step_bytes = sb;
@@ -1140,6 +1207,7 @@ extern "C" int gbs_plan_destroy(gbs_plan* P) {
   if (P->ev_fork) hipEventDestroy(P->ev_fork);
   for (auto& e : P->lf_ev) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   for (auto& e : P->first_ev) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
+  for (auto& e : P->adj_ev) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   delete P;
   return GBS_OK;
 }
@@ -1482,6 +1550,11 @@ extern "C" int gbs_batch_set_graph(gbs_batch_plan* B, int32_t enabled) {
   return GBS_OK;
 }
 
+extern "C" int gbs_batch_set_stream(gbs_batch_plan* B, void* hip_stream) {
+  if (!B) return fail(GBS_EINVAL, "plan is null");
+  return rebind_stream(B->stream, (hipStream_t)hip_stream);
+}
+
 extern "C" int gbs_batch_step(gbs_batch_plan* B, int32_t n_macro, void* const* y) {
   if (!B || !y) return fail(GBS_EINVAL, "null argument");
   if (n_macro < 0) return fail(GBS_EINVAL, "n_macro must be >= 0");
@@ -1657,8 +1730,8 @@ int forward_pairs(gbs_plan* P, double t0, const T* y0, const T* pair_out[GBS_MAX
   pa.src_dev = P->src_dev;
   const int nx = (int)P->prob.n[0];
   constexpr int S = SKEW1 ? R + 1 : R;
-  static const int slots_c = resident_waves(pass2d<T, ORDER, G, SKEW1, 1, false>, 256);
-  static const int slots_v = resident_waves(pass2d<T, ORDER, G, SKEW1, 1, true>, 256);
+  const int slots_c = resident_waves(pass2d<T, ORDER, G, SKEW1, 1, false>, 256);
+  const int slots_v = resident_waves(pass2d<T, ORDER, G, SKEW1, 1, true>, 256);
   const int slots = std::max(1, (P->prob.c2_field ? slots_v : slots_c) / lanes);
   for (int rr = 0; rr < sch.nrounds; ++rr) {
     int n = 0, maxs = 0;
@@ -1742,6 +1815,25 @@ __global__ __launch_bounds__(256) void adj_sum_kernel(const AdjSumArgs<T> a) {
   }
 }
 
+// Algorithmic HBM bytes of one blocked adjoint pass launch over its n
+// sequences: a first pass reads y_N, y_{N-1} and ybar, a later one the two Z
+// levels (Y and Psi, four states); a pass writes two Z levels, or (final)
+// lambda_0 + lambda_1 and h lambda_1 in FP64; the gradient row sums are
+// written (first pass) or read and written (later) once per point and
+// right-hand side; c^2 is read once per launch.
+template <typename T>
+double adj_launch_bytes(const gbs_plan* P, const AdjPassArgs<T>& pa, int n, size_t b) {
+  const double pts = (double)P->field * P->prob.n_rhs;
+  const double Fb = 3.0 * b, F8 = 3.0 * 8;
+  double tot = P->prob.c2_field ? (double)P->field * b : 0.0;
+  for (int i = 0; i < n; ++i) {
+    const AdjPassSeq<T>& d = pa.seq[i];
+    const bool first = d.flags & ADJ_FIRST, final_ = d.flags & ADJ_FINAL;
+    tot += ((first ? 3 * Fb : 4 * Fb) + (final_ ? 2 * F8 : 4 * Fb) + (first ? 8.0 : 16.0)) * pts;
+  }
+  return tot;
+}
+
 template <typename T>
 int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar,
                         double* grad, char* ws, const T* kept = nullptr) {
@@ -1809,8 +1901,8 @@ int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* t
     pa.src_dev = P->src_dev;
     pa.zstride = (int64_t)elems;
     const int nx = (int)P->prob.n[0];
-    static const int slots_c = resident_waves(adj_pass2d<T, G, false>, 256);
-    static const int slots_v = resident_waves(adj_pass2d<T, G, true>, 256);
+    const int slots_c = resident_waves(adj_pass2d<T, G, false>, 256);
+    const int slots_v = resident_waves(adj_pass2d<T, G, true>, 256);
     const int slots = std::max(1, (P->prob.c2_field ? slots_v : slots_c) / L);
     for (int rr = 0; rr < sch.nrounds; ++rr) {
       int n = 0, maxs = 0;
@@ -1855,10 +1947,17 @@ int adjoint_blocked_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* t
       }
       const unsigned blocks = ((unsigned)maxs * pa.nbands + 3) / 4;
       const dim3 grid(blocks, n, P->prob.n_rhs), blk(256);
+      EventPair* ev = nullptr;
+      if (P->timing && L == 1) {
+        ev = &next_event(P->adj_ev, P->adj_used);
+        hipEventRecord(ev->a, ls);
+        P->adj_bytes += adj_launch_bytes(P, pa, n, sizeof(T));
+      }
       if (P->prob.c2_field)
         hipLaunchKernelGGL((adj_pass2d<T, G, true>), grid, blk, 0, ls, pa);
       else
         hipLaunchKernelGGL((adj_pass2d<T, G, false>), grid, blk, 0, ls, pa);
+      if (ev) hipEventRecord(ev->b, ls);
     }
   }  // lanes
   if (L > 1) {

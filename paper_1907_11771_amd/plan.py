@@ -1,6 +1,8 @@
 """A torch-facing wrapper of one library plan: device memory (workspace,
 coefficient field) comes from torch, kernels are enqueued on torch's current
-HIP stream.  No arithmetic of the method happens here."""
+HIP stream (a plan follows the current stream: every call that enqueues work
+first rebinds the library plan when torch's current stream has changed,
+gbs_plan_set_stream).  No arithmetic of the method happens here."""
 import ctypes
 
 import torch
@@ -63,6 +65,13 @@ class GBSPlan:
     def state_shape(self):
         return (self.n_rhs, _FIELDS[self.op]) + tuple(reversed(self.n))
 
+    def _bind_stream(self):
+        """Enqueue on torch's current stream of the plan's device."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            B.check(B.lib().gbs_plan_set_stream(self.handle, cur.cuda_stream))
+            self.stream = cur
+
     def _check_state(self, t):
         if t.device != self.device or t.dtype != self.dtype or not t.is_contiguous():
             raise ValueError("state must be a contiguous %s tensor on %s" % (self.dtype, self.device))
@@ -73,6 +82,7 @@ class GBSPlan:
     def step(self, y, out=None, t0=0.0, n_macro=1):
         """n_macro macro steps from time t0; returns the output tensor (``out``
         may be ``y`` itself)."""
+        self._bind_stream()
         self._check_state(y)
         if out is None:
             out = torch.empty_like(y)
@@ -84,6 +94,7 @@ class GBSPlan:
     def rk4_step(self, y, out=None, t0=0.0, n_steps=1, h=None):
         """n_steps classical RK4 steps of size h (default: the plan's H) with
         the plan's operator; returns the output tensor."""
+        self._bind_stream()
         self._check_state(y)
         if out is None:
             out = torch.empty_like(y)
@@ -94,6 +105,7 @@ class GBSPlan:
         return out
 
     def set_sources(self, rhs, flat_index, weight, f0, delay):
+        self._bind_stream()
         n = len(rhs)
         B.check(B.lib().gbs_plan_set_sources(self.handle, n, B._arr(ctypes.c_int32, rhs),
                                              B._arr(ctypes.c_int64, flat_index),
@@ -102,6 +114,7 @@ class GBSPlan:
 
     def set_receivers(self, rhs, flat_index):
         """Pressure receivers (right-hand side, index within one field)."""
+        self._bind_stream()
         self.n_rec = len(flat_index)
         B.check(B.lib().gbs_plan_set_receivers(self.handle, self.n_rec,
                                                B._arr(ctypes.c_int32, rhs),
@@ -109,6 +122,7 @@ class GBSPlan:
 
     def step_record(self, y, out=None, t0=0.0, n_macro=1, traces=None):
         """As step(), also returning the receiver traces [n_macro, n_rec]."""
+        self._bind_stream()
         self._check_state(y)
         if out is None:
             out = torch.empty_like(y)
@@ -131,6 +145,7 @@ class GBSPlan:
         """One macro step backwards: ybar (adjoint at t0 + H) is replaced by
         the adjoint at t0; trace_bar [n_rec] is the adjoint of the traces
         recorded at t0 + H; dL/dc^2 is added to grad_c2 (FP64)."""
+        self._bind_stream()
         self._check_state(y_in)
         self._check_state(ybar)
         if trace_bar is not None:
@@ -152,6 +167,7 @@ class GBSPlan:
     def step_keep_pairs(self, y, out, pairs, t0=0.0, n_macro=1):
         """As step(), also keeping (y_{N-1}, y_N) of every sequence and macro
         step in ``pairs`` (shape pairs_shape(n_macro), the plan's dtype)."""
+        self._bind_stream()
         self._check_state(y)
         self._check_state(out)
         if (pairs.device != self.device or pairs.dtype != self.dtype
@@ -165,6 +181,7 @@ class GBSPlan:
     def adjoint_step_pairs(self, t0, y_in, pairs, ybar, trace_bar=None, grad_c2=None):
         """adjoint_step() with the forward levels kept by step_keep_pairs
         (``pairs``: that macro step's [k][2] block) instead of recomputed."""
+        self._bind_stream()
         self._check_state(y_in)
         self._check_state(ybar)
         if (pairs.device != self.device or pairs.dtype != self.dtype
@@ -190,6 +207,7 @@ class GBSPlan:
         (gbs_plan_autotune) from ``y`` into ``out`` (a scratch copy if None)
         and keeps the fastest; ``lanes`` > 0 fixes the lane count.  Returns
         (variant, band, lanes)."""
+        self._bind_stream()
         self._check_state(y)
         scratch = y.clone() if out is None else out
         self._check_state(scratch)
@@ -210,6 +228,7 @@ class GBSPlan:
         1, 2 and 3 lanes from the state ``y`` and keeps the fastest count in
         ``adjoint_lanes`` (the forward's lane count is left as it was).
         Returns it, or None when the plan's adjoint is not the blocked one."""
+        self._bind_stream()
         if not self.blocked_adjoint():
             return None
         self._check_state(y)
@@ -261,6 +280,14 @@ class GBSPlan:
         B.check(B.lib().gbs_plan_get_timing(self.handle, ctypes.byref(a), ctypes.byref(b),
                                             ctypes.byref(c), ctypes.byref(d)))
         return a.value, b.value, c.value, d.value
+
+    def get_adjoint_timing(self):
+        """(blocked adjoint pass ms, launches, their algorithmic bytes) since
+        the last read (timing on, one lane)."""
+        a, b, c = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        B.check(B.lib().gbs_plan_get_adjoint_timing(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                                    ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def algorithmic_bytes(self):
         """(stepping-kernel bytes, launches, auxiliary bytes, launches) per
@@ -332,7 +359,15 @@ class GBSBatch:
                                               self.workspace.data_ptr(), self.workspace.numel(),
                                               self.stream.cuda_stream))
 
+    def _bind_stream(self):
+        """Enqueue on torch's current stream of the plan's device."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            B.check(B.lib().gbs_batch_set_stream(self.handle, cur.cuda_stream))
+            self.stream = cur
+
     def _ptrs(self, states):
+        self._bind_stream()
         if len(states) != len(self.shapes):
             raise ValueError("need one state per instance")
         for s, shp in zip(states, self.shapes):

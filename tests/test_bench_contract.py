@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused():
 def test_headline_json_line():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "5",
                         "--warmup", "2", "--no-cpu-baseline"],
-                       capture_output=True, text=True, timeout=300)
+                       capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     line = json.loads(r.stdout.strip().splitlines()[-1])
     for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
@@ -34,3 +34,12 @@ def test_headline_json_line():
     roof = line["roofline"]
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-9
+    # the metric's second half: forward + adjoint at fixed error vs plain,
+    # with the adjoint pass kernel's own roofline
+    fa = line["fwd_adj"]
+    assert fa["unit"] == "s" and fa["value"] > 0
+    assert fa["speedup_vs_plain"]["fp64"] > 1.0
+    assert fa["fp32_stepping"]["grad_c2_rel_err_vs_fp64"] < 1e-3
+    ar = fa["roofline"]
+    assert ar["kernel"].startswith("gbs::adj_pass2d<double") and ar["launches"] > 0
+    assert abs(ar["frac"] - ar["achieved"] / ar["peak"]) < 1e-9

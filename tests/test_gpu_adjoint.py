@@ -45,8 +45,8 @@ def test_adjoint_macro_step_matches_oracle():
     grad = torch.zeros(op.shape, dtype=torch.float64, device="cuda")
     plan.adjoint_step(t0, to_dev(y0[None]), ybar, grad_c2=grad)
     want_y, want_g = AD.macro_step_adjoint(op, t0, y0, H, steps, c, wbar)
-    assert rel_err(ybar.cpu().numpy()[0], want_y) <= 1e-12
-    assert rel_err(grad.cpu().numpy(), want_g) <= 1e-12
+    assert rel_err(ybar.cpu().numpy()[0], want_y, 0) <= 1e-12
+    assert rel_err(grad.cpu().numpy(), want_g, None) <= 1e-12
 
 
 def test_adjoint_3d_fd8_two_rhs_matches_oracle():
@@ -68,9 +68,9 @@ def test_adjoint_3d_fd8_two_rhs_matches_oracle():
     g_total = np.zeros(shape)
     for r in range(2):
         wy, wg = AD.macro_step_adjoint(op, 0.0, y0[r], H, steps, c, wbar[r])
-        assert rel_err(ybar.cpu().numpy()[r], wy) <= 1e-12
+        assert rel_err(ybar.cpu().numpy()[r], wy, 0) <= 1e-12
         g_total += wg
-    assert rel_err(grad.cpu().numpy(), g_total) <= 1e-12
+    assert rel_err(grad.cpu().numpy(), g_total, None) <= 1e-12
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13), (torch.float32, 1e-5)])
@@ -107,8 +107,8 @@ def test_checkpointed_misfit_gradient_matches_oracle(duplicate):
     loss.backward()
     L, gy, gc = AD.misfit_gradient(op, 0.0, y0, H, steps, c, n_macro, rec, data)
     assert float(loss) == pytest.approx(L, rel=1e-12)
-    assert rel_err(y.grad.cpu().numpy()[0], gy) <= 1e-11
-    assert rel_err(c2.grad.cpu().numpy(), gc) <= 1e-11
+    assert rel_err(y.grad.cpu().numpy()[0], gy, 0) <= 1e-11
+    assert rel_err(c2.grad.cpu().numpy(), gc, None) <= 1e-11
 
 
 def test_full_size_gradient_vs_central_differences():
@@ -185,8 +185,8 @@ def test_adjoint_3d_march_matches_flat(dtype, tol):
         grad = torch.zeros(shape, dtype=torch.float64, device="cuda")
         plan.adjoint_step(0.003, y0, ybar, grad_c2=grad)
         res.append((ybar.double().cpu().numpy(), grad.cpu().numpy()))
-    assert rel_err(res[1][0], res[0][0]) <= tol
-    assert rel_err(res[1][1], res[0][1]) <= tol
+    assert rel_err(res[1][0], res[0][0], 1) <= tol
+    assert rel_err(res[1][1], res[0][1], None) <= tol
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
@@ -214,8 +214,8 @@ def test_blocked_adjoint_matches_streaming(dtype, tol, band):
         grad = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
         plan.adjoint_step(0.9 * s["delay"], y0, ybar, grad_c2=grad)
         res.append((ybar.double().cpu().numpy(), grad.cpu().numpy()))
-    assert rel_err(res[1][0], res[0][0]) <= tol
-    assert rel_err(res[1][1], res[0][1]) <= tol
+    assert rel_err(res[1][0], res[0][0], 1) <= tol
+    assert rel_err(res[1][1], res[0][1], None) <= tol
 
 
 def test_blocked_adjoint_lanes_do_not_change_the_result():
@@ -312,3 +312,55 @@ def test_kept_pairs_need_the_blocked_form():
         plan.step_keep_pairs(y, y.clone(), pairs)
     assert ei.value.status == B.GBS_EUNSUPPORTED
     assert not plan.blocked_adjoint()
+
+
+@pytest.mark.parametrize("variant", [B.VARIANT_AUTO, B.VARIANT_FLAT])
+def test_adjoint_with_several_sources_vs_oracle(variant):
+    # the blocked adjoint (and the streaming one) with sources sharing a
+    # column, a point and a strip, in two right-hand sides
+    from tests.test_gpu_parity import multi_source_problem
+    plan, ops, H, t0 = multi_source_problem()
+    plan.set_variant(variant)
+    assert plan.blocked_adjoint() == (variant == B.VARIANT_AUTO)
+    steps, c = oracle_weights(schemes.ORDER8_K6)
+    rng = np.random.default_rng(24)
+    y0 = rng.standard_normal((2, 3) + ops[0].shape)
+    wbar = rng.standard_normal((2, 3) + ops[0].shape)
+    ybar = to_dev(wbar)
+    grad = torch.zeros(ops[0].shape, dtype=torch.float64, device="cuda")
+    plan.adjoint_step(t0, to_dev(y0), ybar, grad_c2=grad)
+    g_total = np.zeros(ops[0].shape)
+    for r in range(2):
+        wy, wg = AD.macro_step_adjoint(ops[r], t0, y0[r], H, steps, c, wbar[r])
+        assert rel_err(ybar.cpu().numpy()[r], wy, 0) <= 1e-12, r
+        g_total += wg
+    assert rel_err(grad.cpu().numpy(), g_total, None) <= 1e-12
+
+
+def test_backward_uses_its_own_forwards_c2():
+    # a second forward with another c^2 between the first forward and its
+    # backward (a line-search probe) must not change the first gradient
+    plan, op, H = _setup2d(nx=32, ny=24)
+    steps, c = oracle_weights(schemes.ORDER8_K6)
+    nx = 32
+    rec = fields.edge_receivers_2d(nx, count=8, row=3)
+    plan.set_receivers([0] * len(rec), [int(r[0]) * nx + int(r[1]) for r in rec])
+    n_macro = 5
+    y0 = fields.acoustic2d_pulse_modes(nx, n_modes=4, kmax=3, width=0.1, seed=9)[:, :24, :]
+    data = np.random.default_rng(6).standard_normal((n_macro, len(rec))) * 1e-2
+    y = to_dev(y0[None]).requires_grad_(True)
+    c2 = plan.c2_field.clone().requires_grad_(True)
+    loss = 0.5 * ((receiver_traces(plan, y, c2, n_macro, checkpoint_every=2)
+                   - to_dev(data)) ** 2).sum()
+    c2b = (1.3 * plan.c2_field).requires_grad_(True)
+    probe = 0.5 * ((receiver_traces(plan, y.detach(), c2b, n_macro) - to_dev(data)) ** 2).sum()
+    loss.backward()
+    L, gy, gc = AD.misfit_gradient(op, 0.0, y0, H, steps, c, n_macro, rec, data)
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-12)
+    assert rel_err(y.grad.cpu().numpy()[0], gy, 0) <= 1e-11
+    assert rel_err(c2.grad.cpu().numpy(), gc, None) <= 1e-11
+    # and the probe's own backward still gives the probe's gradient
+    probe.backward()
+    op_b = OP.Acoustic(op.shape, c2=1.3 * op.c2, r=2, sources=op.sources)
+    _, _, gcb = AD.misfit_gradient(op_b, 0.0, y0, H, steps, c, n_macro, rec, data)
+    assert rel_err(c2b.grad.cpu().numpy(), gcb, None) <= 1e-11

@@ -67,7 +67,7 @@ def test_batch_matches_oracle():
     for y, a, it in zip(ys, y0, inst):
         nx, ny = it["n"]
         want = G.integrate(OP.Acoustic((ny, nx), c2=it["c2np"], r=2), 0.0, a, it["H"], 2, steps, c)
-        assert rel_err(y.cpu().numpy()[0], want) <= 1e-12
+        assert rel_err(y.cpu().numpy()[0], want, 0) <= 1e-12
 
 
 def test_batch_graph_replays_equal_eager():
@@ -106,4 +106,4 @@ def test_batch_autotune_picks_a_candidate():
     other.set_variant(B.VARIANT_TEMPORAL, 64)
     other.step(ref, n_macro=1)
     for a, b in zip(ys, ref):
-        assert rel_err(a.cpu().numpy(), b.cpu().numpy()) <= 1e-13
+        assert rel_err(a.cpu().numpy(), b.cpu().numpy(), 1) <= 1e-13

@@ -32,8 +32,8 @@ def test_advection1d_config_vs_oracle_and_closed_form():
     got = out.cpu().numpy().reshape(1, -1)
     direct = G.integrate(OP.Advection1D(cfg["m"]), 0.0, u0, cfg["H"], cfg["n_macro"], steps, c)
     closed = SP.advection1d(u0, cfg["H"], steps, c, cfg["n_macro"])
-    assert rel_err(got, direct) <= TOL64
-    assert rel_err(got, closed) <= TOL64
+    assert rel_err(got, direct, 0) <= TOL64
+    assert rel_err(got, closed, 0) <= TOL64
 
 
 @pytest.mark.parametrize("shape,order", [((72, 100), 4), ((40, 56), 8), ((33, 17), 4)])
@@ -50,7 +50,7 @@ def test_acoustic2d_constant_c_vs_oracle(shape, order):
     got = out.cpu().numpy()[0]
     want = G.integrate(OP.Acoustic((ny, nx), c2=1.0, r=order // 2), 0.0, y0, H, 4, steps, c)
     for q in range(3):
-        assert rel_err(got[q], want[q]) <= TOL64, q
+        assert rel_err(got[q], want[q], None) <= TOL64, q
 
 
 def test_acoustic2d_variable_c2_with_source_vs_oracle():
@@ -73,7 +73,7 @@ def test_acoustic2d_variable_c2_with_source_vs_oracle():
                      sources=[OP.Source(s["idx"], s["f0"], s["delay"], s["weight"])])
     want = G.integrate(op, t0, y0, H, n_macro, steps, c)
     for q in range(3):
-        assert rel_err(got[q], want[q]) <= TOL64, q
+        assert rel_err(got[q], want[q], None) <= TOL64, q
 
 
 def test_acoustic3d_fd8_variable_c2_multi_rhs_vs_oracle():
@@ -97,7 +97,7 @@ def test_acoustic3d_fd8_variable_c2_multi_rhs_vs_oracle():
         op = OP.Acoustic(shape, c2=c2, r=4, sources=[OP.Source(idx, f0, delay, w_)])
         want = G.integrate(op, 0.0, y0[r], H, 3, steps, c)
         for q in range(4):
-            assert rel_err(got[r, q], want[q]) <= TOL64, (r, q)
+            assert rel_err(got[r, q], want[q], None) <= TOL64, (r, q)
 
 
 def test_in_place_and_repeatable():
@@ -181,7 +181,7 @@ def test_temporal_passes_match_streaming(dtype, variant, band):
             B.check(B.lib().gbs_plan_set_band(plan.handle, band))
         res.append(plan.step(y0, t0=0.3 * s["delay"], n_macro=3).cpu().numpy())
     tol = 1e-13 if dtype == torch.float64 else 2e-6
-    assert rel_err(res[1], res[0]) <= tol
+    assert rel_err(res[1], res[0], 1) <= tol
 
 
 @pytest.mark.parametrize("variant", [B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL_WG4,
@@ -196,7 +196,7 @@ def test_temporal_fd8_matches_oracle(variant):
     plan.set_variant(variant)
     got = plan.step(to_dev(y0[None]), n_macro=3).cpu().numpy()[0]
     want = G.integrate(OP.Acoustic((ny, nx), c2=1.0, r=4), 0.0, y0, H, 3, steps, c)
-    assert rel_err(got, want) <= TOL64
+    assert rel_err(got, want, 0) <= TOL64
 
 
 def test_fp32_stepping_error_vs_fp64():
@@ -211,7 +211,7 @@ def test_fp32_stepping_error_vs_fp64():
     p32 = lib_plan(B.ACOUSTIC2D, (n, n), sch, H, dtype=torch.float32)
     a = p64.step(to_dev(y0[None]), n_macro=20).cpu().numpy()
     b = p32.step(to_dev(y0[None], torch.float32), n_macro=20).cpu().numpy()
-    err = rel_err(b, a)
+    err = rel_err(b, a, 1)
     print("fp32 vs fp64 rel err", err)
     assert err <= 2e-5
 
@@ -231,8 +231,7 @@ def test_acoustic2d_full_size_500_steps_vs_closed_form():
     out = plan.step(y, n_macro=cfg["n_macro"])
     got = out.cpu().numpy()[0]
     want = SP.acoustic(y0, 1.0, cfg["H"], steps, c, cfg["n_macro"])
-    errs = [rel_err(got[q], want[q]) if q == 0 else
-            float(np.max(np.abs(got[q] - want[q])) / np.max(np.abs(want[0]))) for q in range(3)]
+    errs = [rel_err(got[q], want[q], None) for q in range(3)]
     print("full-size rel errors", errs)
     assert max(errs) <= TOL64
 
@@ -255,7 +254,7 @@ def test_plan_autotune_keeps_a_blocked_variant_with_the_same_result():
     assert band in (0, 32, 64, 96, 128)
     assert plan.variant() == v
     got = plan.step(y0, n_macro=2).cpu().numpy()
-    assert rel_err(got, want) <= 1e-13
+    assert rel_err(got, want, 1) <= 1e-13
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -277,3 +276,68 @@ def test_lanes_do_not_change_the_result(dtype):
         outs.append(plan.step(y0, t0=0.3 * s["delay"], n_macro=4))
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
+
+
+# Several point sources through the temporally blocked passes: two in one
+# grid column of right-hand side 0 (rows 20 and 61), a third at the first
+# one's point, a fourth in another column of the same 64-column strip, and
+# one in right-hand side 1.  (rhs, (iy, ix), weight factor)
+MULTI_SOURCES = [(0, (20, 30), 1.0), (0, (61, 30), -0.7), (0, (20, 30), 0.4),
+                 (0, (45, 33), 0.9), (1, (50, 90), 1.3)]
+
+
+def multi_source_problem(dtype=torch.float64):
+    ny, nx = 90, 100
+    cs = fields.lognormal_speed((ny, nx), seed=22)
+    c2 = cs ** 2
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(nx, ny), 2,
+                           workloads.SIGMA_FD4)
+    s = fields.ricker_source_2d(max(nx, ny), cells_per_wavelength=6.0)
+    w0 = s["weight"] * 1e-3
+    plan = lib_plan(B.ACOUSTIC2D, (nx, ny), schemes.ORDER8_K6, H, n_rhs=2, dtype=dtype,
+                    c2_field=to_dev(c2, dtype), c_max=float(cs.max()))
+    plan.set_sources([r for r, _, _ in MULTI_SOURCES],
+                     [iy * nx + ix for _, (iy, ix), _ in MULTI_SOURCES],
+                     [w0 * k for _, _, k in MULTI_SOURCES], s["f0"], s["delay"])
+    ops = [OP.Acoustic((ny, nx), c2=c2, r=2,
+                       sources=[OP.Source(idx, s["f0"], s["delay"], w0 * k)
+                                for rr, idx, k in MULTI_SOURCES if rr == r])
+           for r in range(2)]
+    t0 = s["delay"] - 2 * H               # the wavelet near its peak
+    return plan, ops, H, t0
+
+
+@pytest.mark.parametrize("variant", [B.VARIANT_AUTO, B.VARIANT_TEMPORAL_S5, B.VARIANT_TEMPORAL,
+                                     B.VARIANT_FLAT])
+def test_blocked_passes_with_several_sources_vs_oracle(variant):
+    plan, ops, H, t0 = multi_source_problem()
+    steps, c = oracle_weights(schemes.ORDER8_K6)
+    plan.set_variant(variant)
+    rng = np.random.default_rng(23)
+    y0 = 1e-3 * rng.standard_normal((2, 3) + ops[0].shape)
+    got = plan.step(to_dev(y0), t0=t0, n_macro=3).cpu().numpy()
+    for r in range(2):
+        want = G.integrate(ops[r], t0, y0[r], H, 3, steps, c)
+        assert rel_err(got[r], want, 0) <= TOL64, r
+
+
+def test_plan_follows_torchs_current_stream():
+    # a plan created on one stream and called under another enqueues on the
+    # current one (ordered after the old one's work), with the same results
+    n = 96
+    sch = schemes.ORDER8_K6
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, 1.0, 1.0 / n, 2, workloads.SIGMA_FD4)
+    y0 = to_dev(np.random.default_rng(10).standard_normal((1, 3, n, n)))
+    plan = lib_plan(B.ACOUSTIC2D, (n, n), sch, H)
+    want = plan.step(y0, n_macro=3)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        got = plan.step(y0, n_macro=3)
+        assert plan.stream.cuda_stream == s.cuda_stream
+        got2 = plan.step(got, n_macro=2)
+    torch.cuda.current_stream().wait_stream(s)
+    assert torch.equal(got, want)
+    back = plan.step(want, n_macro=2)
+    assert plan.stream.cuda_stream == torch.cuda.current_stream().cuda_stream
+    assert torch.equal(back, got2)
