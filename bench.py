@@ -109,6 +109,10 @@ def summarize_counters(args):
     is_copy = lambda k: "copy" in k.lower() or "elementwise" in k.lower()
     f = per_dispatch(fetch, "FETCH_SIZE", is_kernel)
     w = per_dispatch(write, "WRITE_SIZE", is_kernel)
+    if args.last:
+        # the timed region's launches only (the autotuner's trial launches
+        # of the same kernel come first)
+        f, w = f[-args.last:], w[-args.last:]
     cf = per_dispatch(cfetch, "FETCH_SIZE", is_copy)
     cw = per_dispatch(cwrite, "WRITE_SIZE", is_copy)
     if not (f and w and cf and cw):
@@ -712,6 +716,10 @@ def main():
                     help="stepping-kernel variant (0: autotuned by the library)")
     ap.add_argument("--band", type=int, default=0,
                     help="rows per band of the temporally blocked passes (0 = default)")
+    ap.add_argument("--form", type=int, default=None,
+                    help="GBS_FORM_* flags of the blocked passes (gbs_plan_set_form)")
+    ap.add_argument("--wave-order", type=int, default=None,
+                    help="workgroup order of the blocked passes (gbs_plan_set_wave_order)")
     ap.add_argument("--workload", default="acoustic2d",
                     choices=["acoustic2d", "batch64", "adjoint1024", "acoustic3d", "rk4",
                              "oneway"],
@@ -729,6 +737,8 @@ def main():
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="print the TRAFFIC line of --kernel from rocprofv3 counter files")
     ap.add_argument("--kernel", help="kernel name for --summarize-counters")
+    ap.add_argument("--last", type=int, default=0,
+                    help="--summarize-counters: only the last LAST launches of the kernel")
     ap.add_argument("--counters-workload", help="workload name for --summarize-counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (the reference "
@@ -789,6 +799,10 @@ def main():
         # duration (the roofline figure) is not shared with a concurrent one.
         tuned = plan.autotune(y, out, macro_steps=5, lanes=1)
 
+    if args.wave_order is not None:
+        B.check(B.lib().gbs_plan_set_wave_order(plan.handle, args.wave_order))
+    if args.form is not None:
+        B.check(B.lib().gbs_plan_set_form(plan.handle, args.form))
     plan.step(y, out, n_macro=args.warmup)
     torch.cuda.synchronize()
     # timed region: K macro steps; every launch is bracketed by HIP events on

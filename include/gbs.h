@@ -261,6 +261,35 @@ enum {
 };
 int gbs_plan_set_variant(gbs_plan* plan, int32_t variant);
 int gbs_plan_set_band(gbs_plan* plan, int32_t rows);
+/*
+ * gbs_plan_set_wave_order — order of the temporally blocked passes'
+ * workgroups (a tuning knob; results do not change): 0 (default) one grid
+ * row per sequence; 1 and 2 put the sequences of one group of 4 strips next
+ * to each other on one XCD (workgroups reach the 8 XCDs round-robin), so
+ * that first passes reading the same y_0 rows share an L2, with the groups
+ * round-robin over the XCDs (1) or contiguous per XCD (2).  Errors:
+ * GBS_EINVAL for a null plan or another value.
+ */
+int gbs_plan_set_wave_order(gbs_plan* plan, int32_t order);
+/*
+ * gbs_plan_set_form — how the temporally blocked passes organise a macro
+ * step (flags; results agree to rounding):
+ *   GBS_FORM_SHARED_F0      f(t_0, y_0) evaluated once per macro step by a
+ *                           kernel of its own and shared by the first passes
+ *                           of all sequences (Sect. 3.6), which then start
+ *                           from (y_0, y_0 + h_j F_0); without it every first
+ *                           pass evaluates f(t_0, y_0) itself
+ *   GBS_FORM_FUSED_COMBINE  when the largest-N sequence's final pass is alone
+ *                           in the last launch (and the plan runs on one
+ *                           lane), that pass also forms y_out = sum_j c_j y*_j
+ *                           instead of a separate combination kernel
+ * Default: 0 (neither: on the 2-D workload both measured slower, the shared
+ * F_0 doubling the first passes' reads and the fused tail running one
+ * sequence's wavefronts alone).  Errors: GBS_EINVAL (null plan, unknown
+ * flags).
+ */
+enum { GBS_FORM_SHARED_F0 = 1, GBS_FORM_FUSED_COMBINE = 2 };
+int gbs_plan_set_form(gbs_plan* plan, int32_t form);
 int gbs_plan_get_variant(const gbs_plan* plan, int32_t* variant);
 
 /*

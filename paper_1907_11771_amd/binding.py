@@ -22,6 +22,7 @@ VARIANT_MARCH8_NT, VARIANT_MARCH16_NT = 4, 5
 VARIANT_TEMPORAL, VARIANT_TEMPORAL4, VARIANT_TEMPORAL_S5, VARIANT_TEMPORAL_S6 = 6, 7, 8, 9
 VARIANT_PLAIN = 10
 VARIANT_TEMPORAL_WG4, VARIANT_TEMPORAL_WG8 = 11, 12
+FORM_SHARED_F0, FORM_FUSED_COMBINE = 1, 2
 MAX_SEQ = 16
 MAX_SRC = 16
 MAX_REC = 1024
@@ -82,6 +83,8 @@ def lib():
             "gbs_plan_autotune": [vp, vp, vp, i32, P(i32), P(i32), P(i32)],
             "gbs_plan_set_lanes": [vp, i32],
             "gbs_plan_set_band": [vp, i32],
+            "gbs_plan_set_wave_order": [vp, i32],
+            "gbs_plan_set_form": [vp, i32],
             "gbs_plan_set_stream": [vp, vp],
             "gbs_plan_get_timing": [vp, P(dbl), P(i64), P(dbl), P(i64)],
             "gbs_plan_get_adjoint_timing": [vp, P(dbl), P(i64), P(dbl)],

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -87,6 +88,8 @@ struct gbs_plan {
   // temporally blocked passes
   int variant = 0;
   int band = 0;            // 0: chosen per launch
+  int wave_order = 0;      // workgroup order of the blocked passes (PassArgs::order)
+  int form = 0;            // GBS_FORM_* flags of the blocked passes
   // temporally blocked layout: per sequence two pairs of levels
   void* pair[GBS_MAX_SEQ][2][2];
   // gbs_step_keep_pairs: caller's buffer for (y_{N-1}, y_N) of every
@@ -458,12 +461,52 @@ int band_for_round(const gbs_plan* P, int total_strips, int gmax, int R, int S, 
   return best;
 }
 
+// The tail kernel of the shared form: the last sequence's final pass with
+// the combination (at most COMB_G evaluations).
+constexpr int COMB_G = 4;
+
+// How a temporally blocked macro step is organised: the pass schedule;
+// whether f(t_0, y_0) is shared (one f0_march2d launch, first passes start
+// from (y_0, y_1)); and whether the combination is folded into the last
+// sequence's final pass, which needs that pass alone in the last round
+// (every other y* is complete by then), at most COMB_G evaluations in it,
+// at most COMB_MAX other sequences, one lane and no kept levels.
+struct TemporalForm {
+  PassSchedule sch;
+  bool shared_f0 = true;
+  bool fuse = false;
+};
+
+int temporal_form(const gbs_plan* P, int G, int R, int wpg, int order, TemporalForm& f) {
+  f.shared_f0 = (P->form & GBS_FORM_SHARED_F0) != 0;
+  int st = make_schedule(P->steps, P->k, G, R, wpg, f.sch, false, f.shared_f0 ? 0 : 1);
+  if (st) return st;
+  const PassSchedule& sch = f.sch;
+  const int jl = P->order[P->k - 1];
+  int last_round_seqs = 0;
+  for (int j = 0; j < P->k; ++j)
+    if (sch.round0[j] + sch.npass[j] == sch.nrounds) ++last_round_seqs;
+  const int L = std::max(1, std::min(P->lanes, P->k));
+  f.fuse = (P->form & GBS_FORM_FUSED_COMBINE) && order == 4 && wpg == 1 && L == 1 &&
+           !P->keep_out && P->k >= 2 &&
+           P->k - 1 <= COMB_MAX && last_round_seqs == 1 &&
+           sch.round0[jl] + sch.npass[jl] == sch.nrounds &&
+           sch.gsz[jl][sch.npass[jl] - 1] <= COMB_G;
+  return GBS_OK;
+}
+
 template <typename T, int ORDER, int G, bool SKEW1, int WPG>
 int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   constexpr int R = Fd<ORDER>::R;
-  PassSchedule sch;
-  int st = make_schedule(P->steps, P->k, G, R, WPG, sch);
+  // f(t_0, y_0) evaluated once per macro step (f0_march2d) and shared by the
+  // first passes of all sequences, each of which then performs N_j
+  // evaluations; F_0 lives in the plan's FP64 accumulator space
+  TemporalForm form;
+  int st = temporal_form(P, G, R, WPG, ORDER, form);
   if (st) return st;
+  const PassSchedule& sch = form.sch;
+  const bool shared_f0 = form.shared_f0;
+  const bool fuse = form.fuse;
   const int* npass = sch.npass;
   PassArgs<T> pa;
   std::memset(&pa, 0, sizeof(pa));
@@ -471,6 +514,19 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   fill_geometry<T>(P, pa.g, c2c, pa.c2f, pa.invx, pa.invy, invz);
   pa.c2c = c2c;
   pa.src_dev = P->src_dev;
+  pa.f0 = shared_f0 ? (const T*)P->acc : nullptr;
+  F0Args<T> fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.f0 = (T*)P->acc;
+  fa.c2f = pa.c2f;
+  fa.src = P->src_dev;
+  fa.g = pa.g;
+  fa.c2c = c2c;
+  fa.invx = pa.invx;
+  fa.invy = pa.invy;
+  constexpr int F0_TY = 16;
+  const unsigned f0_blocks =
+      (unsigned)(((P->prob.n[0] + 63) / 64) * ((P->prob.n[1] + 4 * F0_TY - 1) / (4 * F0_TY)));
   const int nx = (int)P->prob.n[0];
   constexpr int S = SKEW1 ? R + 1 : R;
   const int slots_c = resident_waves(pass2d<T, ORDER, G, SKEW1, WPG, false>,
@@ -495,9 +551,37 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
   int lane_of[GBS_MAX_SEQ];
   for (int r = 0; r < P->k; ++r) lane_of[r] = std::min(r, P->k - 1 - r) % L;
   const int lane_slots = std::max(1, slots / L);
+  // the combination folded into the last sequence's final pass (see
+  // temporal_form)
+  if (fuse) {
+    for (int r = 0; r + 1 < P->k; ++r) {
+      pa.comb.ystar[r] = ca.ystar[r];
+      pa.comb.c[r] = ca.c[r];
+    }
+    pa.comb.n = P->k - 1;
+    pa.comb.c_last = ca.c[P->k - 1];
+    pa.comb.yout = yout;
+  }
+  const int slots_comb =
+      fuse ? (P->prob.c2_field
+                  ? resident_waves(pass2d<T, ORDER, COMB_G, true, 1, true, false, true>, 256)
+                  : resident_waves(pass2d<T, ORDER, COMB_G, true, 1, false, false, true>, 256))
+           : 0;
   for (int m = 0; m < n_macro; ++m) {
     const double t = t0 + m * P->H;
     const T* y0 = m == 0 ? yin : yout;
+    if (shared_f0) {
+      fa.y0 = y0;
+      fa.amp = P->nsrc ? ricker(t, P->f0, P->delay) : 0.0;
+      EventPair* ev = nullptr;
+      if (P->timing) {
+        ev = &next_event(P->first_ev, P->first_used);
+        hipEventRecord(ev->a, P->stream);
+      }
+      hipLaunchKernelGGL((f0_march2d<T, ORDER, F0_TY>), dim3(f0_blocks, 1, P->prob.n_rhs),
+                         dim3(256), 0, P->stream, fa);
+      if (ev) hipEventRecord(ev->b, P->stream);
+    }
     if (L > 1) {
       hipEventRecord(P->ev_fork, P->stream);
       for (int l = 1; l < L; ++l) hipStreamWaitEvent(P->lane_stream[l], P->ev_fork, 0);
@@ -512,13 +596,17 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         if (lane_of[r] != l || q < 0 || q >= npass[j]) continue;
         PassSeq<T>& d = pa.seq[n++];
         const double h = P->H / P->steps[j];
-        int s0 = 0;             // the pass's input level is y_{s0}: s0 = evaluations so far
+        // the pass's input level is y_{s0}: s0 = evaluations so far (the
+        // shared form's first pass starts from the pair (y_0, y_1))
+        int s0 = shared_f0 ? 1 : 0;
         for (int qq = 0; qq < q; ++qq) s0 += sch.gsz[j][qq];
         d.g = sch.gsz[j][q];
         d.h = (T)h;
-        d.flags = (q == 0 ? PASS_FIRST : 0) | (q == npass[j] - 1 ? PASS_FINAL : 0);
+        d.flags = (q == 0 ? (shared_f0 ? PASS_F0 : PASS_FIRST) : 0) |
+                  (q == npass[j] - 1 ? PASS_FINAL : 0);
+        if (fuse && rr == sch.nrounds - 1) d.flags |= PASS_COMBINE;
         d.cur = q == 0 ? y0 : (const T*)P->pair[j][(q - 1) % 2][1];
-        d.old = q == 0 ? nullptr : (const T*)P->pair[j][(q - 1) % 2][0];
+        d.old = q == 0 ? (shared_f0 ? y0 : nullptr) : (const T*)P->pair[j][(q - 1) % 2][0];
         d.out_a = (T*)P->pair[j][q % 2][0];
         d.out_b = (T*)P->pair[j][q % 2][1];
         d.ystar = (double*)P->pair[j][q % 2][0];
@@ -542,7 +630,9 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
           strips += pa.seq[i].strips;
           gmax = std::max(gmax, pa.seq[i].g);
         }
-        pa.band = band_for_round(P, strips, gmax, R, S, L > 1 ? lane_slots : slots);
+        const bool tail = fuse && rr == sch.nrounds - 1;
+        pa.band = band_for_round(P, strips, gmax, R, tail ? R + 1 : S,
+                                 tail ? slots_comb : (L > 1 ? lane_slots : slots));
         pa.nbands = (int)((P->prob.n[1] + pa.band - 1) / pa.band);
       }
       const unsigned waves = (unsigned)maxs * pa.nbands;
@@ -552,7 +642,28 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         hipEventRecord(ev->a, ls);
       }
       const unsigned blocks = WPG > 1 ? waves : (waves + 3) / 4;
-      const dim3 grid(blocks, n, P->prob.n_rhs), blk(WPG > 1 ? 64 * WPG : 256);
+      dim3 grid(blocks, n, P->prob.n_rhs);
+      const dim3 blk(WPG > 1 ? 64 * WPG : 256);
+      pa.order = WPG == 1 && n > 1 ? P->wave_order : 0;
+      if (pa.order) {
+        // sequences of one group of 4 units adjacent on one XCD
+        pa.nseq = n;
+        pa.per = (int)((blocks + 7) / 8);
+        grid = dim3(8u * (unsigned)pa.per * (unsigned)n, 1, P->prob.n_rhs);
+      }
+      if constexpr (ORDER == 4 && WPG == 1) {
+        if (fuse && rr == sch.nrounds - 1) {
+          // the last sequence's final pass, forming y_out
+          if (P->prob.c2_field)
+            hipLaunchKernelGGL((pass2d<T, ORDER, COMB_G, true, 1, true, false, true>), grid, blk,
+                               0, ls, pa);
+          else
+            hipLaunchKernelGGL((pass2d<T, ORDER, COMB_G, true, 1, false, false, true>), grid, blk,
+                               0, ls, pa);
+          if (ev) hipEventRecord(ev->b, ls);
+          continue;
+        }
+      }
       // the kept-pairs stores live in their own instantiations so that the
       // plain forward kernels keep their register budget
       if constexpr (ORDER == 4) {
@@ -577,6 +688,7 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         hipStreamWaitEvent(P->stream, P->ev_join[l], 0);
       }
     }
+    if (fuse) continue;     // the last pass has formed y_out
     EventPair* ev = nullptr;
     if (P->timing) {
       ev = &next_event(P->first_ev, P->first_used);
@@ -811,11 +923,13 @@ extern "C" int gbs_plan_workspace_bytes(const gbs_problem* prob, const gbs_schem
   return GBS_OK;
 }
 
-extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gbs_scheme* sch,
-                               double H, void* workspace, size_t ws_bytes, void* hip_stream) {
+namespace {
+
+// Validates the problem and scheme and sets up *P (a default-constructed
+// plan) on the caller's workspace.
+int plan_init(gbs_plan* P, const gbs_problem* prob, const gbs_scheme* sch, double H,
+              void* workspace, size_t ws_bytes, void* hip_stream) {
   try {
-    if (!out) return fail(GBS_EINVAL, "out is null");
-    *out = nullptr;
     int st = validate_problem(prob);
     if (st) return st;
     st = validate_scheme(sch);
@@ -828,7 +942,6 @@ extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gb
       return fail(GBS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
     st = check_stable(prob, sch, H);
     if (st) return st;
-    gbs_plan* P = new gbs_plan();
     P->prob = *prob;
     P->k = sch->k;
     for (int j = 0; j < sch->k; ++j) {
@@ -865,11 +978,27 @@ extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gb
         for (int q = 0; q < 2; ++q)
           for (int l = 0; l < 2; ++l) P->pair[j][q][l] = sb + (2 * q + l) * lb;
     }
-    *out = P;
     return GBS_OK;
   } catch (const std::exception& e) {
     return fail(GBS_EINVAL, "gbs_plan_create: %s", e.what());
   }
+}
+
+}  // namespace
+
+extern "C" int gbs_plan_create(gbs_plan** out, const gbs_problem* prob, const gbs_scheme* sch,
+                               double H, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out) return fail(GBS_EINVAL, "out is null");
+  *out = nullptr;
+  gbs_plan* P = new (std::nothrow) gbs_plan();
+  if (!P) return fail(GBS_ENOMEM, "out of host memory");
+  const int st = plan_init(P, prob, sch, H, workspace, ws_bytes, hip_stream);
+  if (st) {
+    delete P;
+    return st;
+  }
+  *out = P;
+  return GBS_OK;
 }
 
 extern "C" int gbs_plan_set_sources(gbs_plan* P, int32_t n_src, const int32_t* rhs,
@@ -964,6 +1093,21 @@ extern "C" int gbs_plan_set_band(gbs_plan* P, int32_t rows) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
   if (rows < 0 || rows > (1 << 20)) return fail(GBS_EINVAL, "rows per band out of range");
   P->band = rows;
+  return GBS_OK;
+}
+
+extern "C" int gbs_plan_set_form(gbs_plan* P, int32_t form) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  if (form & ~(GBS_FORM_SHARED_F0 | GBS_FORM_FUSED_COMBINE))
+    return fail(GBS_EINVAL, "unknown form flags 0x%x", form);
+  P->form = form;
+  return GBS_OK;
+}
+
+extern "C" int gbs_plan_set_wave_order(gbs_plan* P, int32_t order) {
+  if (!P) return fail(GBS_EINVAL, "plan is null");
+  if (order < 0 || order > 2) return fail(GBS_EINVAL, "wave order must be 0, 1 or 2");
+  P->wave_order = order;
   return GBS_OK;
 }
 
@@ -1151,20 +1295,32 @@ extern "C" int gbs_plan_algorithmic_bytes(const gbs_plan* P, double* step_bytes,
   double sb = 0, ab = 0;
   int64_t sl = 0, al = 0;
   if (P->prob.op == GBS_ACOUSTIC2D && is_temporal(v)) {
-    const int Gx = temporal_shape(v, P->prob.fd_order).G;
-    int maxpass = 0;
+    const TemporalShape ts = temporal_shape(v, P->prob.fd_order);
+    TemporalForm form;
+    const int st = temporal_form(P, ts.G, P->prob.fd_order / 2, ts.wpg, P->prob.fd_order, form);
+    if (st) return st;
+    const PassSchedule& sch = form.sch;
+    const int jl = P->order[P->k - 1];
     for (int j = 0; j < P->k; ++j) {
-      const int E = P->steps[j] + 1, np = (E + Gx - 1) / Gx;
-      maxpass = std::max(maxpass, np);
+      const int np = sch.npass[j];
       for (int q = 0; q < np; ++q) {
         if (q > 0) sb += 2 * Fb * pts;                       // the pair of levels in
-        sb += (q == np - 1 ? F8 : 2 * Fb) * pts;             // the pair out, or y*
+        if (q < np - 1) sb += 2 * Fb * pts;                  // the pair out
+        else if (form.fuse && j == jl) sb += ((P->k - 1) * F8 + Fb) * pts;  // other y*, y_out
+        else sb += F8 * pts;                                 // y*
       }
     }
-    sl = maxpass;
-    sb += Fb * pts + sl * c2b;                               // y0 (round 0), c^2 per launch
-    ab = ((double)P->k * F8 + Fb) * pts;                     // combine
-    al = 1;
+    sl = sch.nrounds;
+    // round 0 reads y0 (and F_0) once; c^2 once per launch
+    sb += (form.shared_f0 ? 2 : 1) * Fb * pts + sl * c2b;
+    if (form.shared_f0) {
+      ab += 2 * Fb * pts + c2b;                              // f(t0, y0): y0 in, F_0 out
+      al += 1;
+    }
+    if (!form.fuse) {
+      ab += ((double)P->k * F8 + Fb) * pts;                  // combine
+      al += 1;
+    }
   } else {
     for (int r = 0; r < P->k; ++r) {
       const int N = P->steps[P->order[r]];
@@ -1195,8 +1351,10 @@ extern "C" int gbs_plan_updates_per_macro_step(const gbs_plan* P, double* update
   return GBS_OK;
 }
 
-extern "C" int gbs_plan_destroy(gbs_plan* P) {
-  if (!P) return GBS_OK;
+namespace {
+
+// Releases what a plan created besides itself (lane streams, events).
+void plan_release(gbs_plan* P) {
   for (int l = 1; l < GBS_MAX_LANES; ++l) {
     if (P->lane_stream[l]) {
       hipStreamSynchronize(P->lane_stream[l]);
@@ -1208,9 +1366,17 @@ extern "C" int gbs_plan_destroy(gbs_plan* P) {
   for (auto& e : P->lf_ev) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   for (auto& e : P->first_ev) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
   for (auto& e : P->adj_ev) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
+}
+
+}  // namespace
+
+extern "C" int gbs_plan_destroy(gbs_plan* P) {
+  if (!P) return GBS_OK;
+  plan_release(P);
   delete P;
   return GBS_OK;
 }
+
 
 extern "C" const char* gbs_last_error(void) { return g_last_error.c_str(); }
 

@@ -2,12 +2,18 @@
 //
 // A pass advances one sequence by up to G evaluations of f in one launch, so
 // that the intermediate levels never leave the chip.  The first pass of a
-// sequence starts from y_0 and performs the forward Euler step (Sect. 2.1,
-// eq. GBS; the evaluation f(t_0, y_0) is repeated per sequence, which the
-// paper allows in place of sharing it, Sect. 3.6); later passes start from
-// the two levels the previous pass stored.  The last pass applies the
-// averaging y* = (y_{N-1} + 2 y_N + y_{N+1}) / 4 and stores y* in FP64; a
-// separate kernel forms sum_j c_j y*_j in ascending N (Sect. 3.2).
+// sequence starts from y_0.  In the shared form (PASS_F0) the evaluation
+// f(t_0, y_0) is done once per macro step by f0_march2d, as Sect. 3.6 shares
+// it, and the first pass of every sequence starts from the pair
+// (y_0, y_1 = y_0 + h F_0), formed as it loads its input rows; otherwise
+// (PASS_FIRST) the first pass evaluates f(t_0, y_0) itself and performs the
+// forward Euler step (Sect. 2.1, eq. GBS).  Later passes start from the two
+// levels the previous pass stored.  The last pass applies the averaging
+// y* = (y_{N-1} + 2 y_N + y_{N+1}) / 4 and stores y* in FP64; a separate
+// kernel forms sum_j c_j y*_j in ascending N (Sect. 3.2), or, when the
+// sequence with the largest N is the only one left in the last launch, its
+// final pass does (PASS_COMBINE, kernels instantiated with COMB): at every
+// output row it reads the other sequences' y* and stores y_out.
 //
 // Work layout: one wavefront owns a strip of 64 consecutive columns and a
 // band of rows, and marches down the band.  Level A_e (e = 0 is the pass's
@@ -29,7 +35,10 @@ constexpr int PASS_FIRST = 1;   // input is y_0; evaluation 1 is forward Euler
 constexpr int PASS_FINAL = 2;   // output is y* (FP64) instead of two levels
 constexpr int PASS_KEEP = 4;    // final pass also stores (y_{N-1}, y_N) to out_a, out_b
                                 // (only in kernels instantiated with KEEP = true)
+constexpr int PASS_F0 = 8;      // first pass of the shared form: old = y_0, cur = y_0 + h F_0
+constexpr int PASS_COMBINE = 16;  // final pass stores y_out = sum_j c_j y*_j (COMB kernels)
 constexpr int PASS_GMAX = 8;
+constexpr int COMB_MAX = 5;     // y* of other sequences a combining pass reads per point
 
 template <typename T>
 struct PassSeq {
@@ -46,17 +55,37 @@ struct PassSeq {
   double amp[PASS_GMAX];  // source wavelet at each evaluation's time
 };
 
+// The combination a PASS_COMBINE pass forms: y_out = sum_r c[r] y*_r (the
+// other sequences, ascending N) + c_last y*_this, summed in that order.
+template <typename T>
+struct CombineTail {
+  const double* ystar[COMB_MAX];
+  double c[COMB_MAX];
+  double c_last;
+  T* yout;
+  int32_t n;          // sequences in ystar (1..COMB_MAX)
+};
+
 template <typename T>
 struct PassArgs {
   PassSeq<T> seq[GBS_MAX_SEQ];
   const SrcDesc* src_dev;    // device copy of the point sources
   Geometry g;
   const T* c2f;
+  const T* f0;        // F_0 = f(t_0, y_0) for PASS_F0 passes (state-sized) or null
   T c2c;
   T invx, invy;
   int32_t band;       // rows per band
   int32_t nbands;
   int32_t max_strips;
+  // order of the workgroups (WPG = 1): 0: blockIdx.y is the sequence;
+  // 1, 2: a 1-D grid in which the nseq sequences of one group of 4 units
+  // (4 strips of a band) are consecutive workgroups of one XCD (workgroups
+  // go to the 8 XCDs round-robin), so that first passes reading the same
+  // y_0 rows share that XCD's L2; groups round-robin over the XCDs (1) or
+  // contiguous per XCD, `per` groups each (2)
+  int32_t order, nseq, per;
+  CombineTail<T> comb;
 };
 
 // Cross-lane moves over the whole wavefront: lane l receives the value of
@@ -106,6 +135,9 @@ struct PassWork {
   T* out_b;            // non-final: A_g
   double* ystar;       // final: y* (FP64)
   const T* c2f;        // coefficient field or null
+  const T* f0;         // PASS_F0: F_0 of this right-hand side
+  const CombineTail<T>* comb;   // PASS_COMBINE: the combination (kernel arguments)
+  int64_t rhs_off;     // PASS_COMBINE: offset of this right-hand side's state
   const SrcDesc* src;  // device array of point sources (global memory) or null
   int64_t field;       // points per field
   int64_t rhs;         // right-hand-side index (for sources)
@@ -159,7 +191,8 @@ __device__ __forceinline__ T lane_dsum_edges(T u, int lane, const T* left, const
   return s;
 }
 
-template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC, bool KEEP = false>
+template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC, bool KEEP = false,
+          bool COMB = false>
 __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, const int band) {
   constexpr int R = Fd<ORDER>::R;
   constexpr int S = SKEW1 ? R + 1 : R;               // rows between consecutive levels
@@ -185,14 +218,33 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
   const int niter = (yb - ya) + halo + g * S;        // until A_g reaches row yb - 1
   const int64_t F1 = w.field, F2 = 2 * w.field;
   const bool first = w.flags & PASS_FIRST;
+  const bool f0mode = w.flags & PASS_F0;             // old = y_0, cur = y_0 + h F_0
   const bool final_ = w.flags & PASS_FINAL;
   const bool keep = KEEP && (w.flags & PASS_KEEP);   // compiled only where asked for
+  const bool comb = COMB && (w.flags & PASS_COMBINE);
   constexpr bool varc = VARC;                       // c^2 field (else the constant)
   const LaneSource ls = w.nsrc > 0 ? lane_source(w.src, w.nsrc, w.rhs, gx, nx) : LaneSource();
   const bool srcs = ls.any;
   const T fac_lf = T(2) * w.h;
   const T* __restrict__ cur = w.cur + gx;
-  const T* __restrict__ old = first ? cur : w.old + gx;
+  const T* __restrict__ old = (first || f0mode) ? cur : w.old + gx;
+  const T* __restrict__ f0p = f0mode ? w.f0 + gx : nullptr;
+  // PASS_COMBINE: the other sequences' y* at the next output row, loaded one
+  // row step before they are summed
+  double pre[COMB ? COMB_MAX : 1][3];
+  const int ncomb = comb ? w.comb->n : 0;
+  auto prefetch = [&](int yr) {
+    if constexpr (COMB) {
+      const int64_t pn = w.rhs_off + (int64_t)yr * nx + gx;
+#pragma unroll
+      for (int r = 0; r < COMB_MAX; ++r)
+        if (r < ncomb) {
+          const double* yp = w.comb->ystar[r] + pn;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) pre[r][q] = __builtin_nontemporal_load(yp + q * F1);
+        }
+    }
+  };
 
   T W[G][P][3];
 #pragma unroll
@@ -233,6 +285,13 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
         nxt[0] = cur[e0];
         nxt[1] = cur[e0 + F1];
         nxt[2] = cur[e0 + F2];
+        if (f0mode) {
+          // y_1 = y_0 + h F_0, the forward Euler step every sequence shares
+          // the evaluation of
+          const T f0v[3] = {f0p[e0], f0p[e0 + F1], f0p[e0 + F2]};
+#pragma unroll
+          for (int q = 0; q < 3; ++q) nxt[q] = nxt[q] + w.h * f0v[q];
+        }
         if constexpr (VARC) c2new = w.c2f[e0 + gx];
         if (!first) {
           const int64_t e1 = (int64_t)wrap_sub(irow, S, ny) * nx;
@@ -333,9 +392,18 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
                 const T ym1 = (e >= 2) ? W[e >= 2 ? e - 2 : 0][c][q] : (first ? In[c][q] : om[q]);
-                __builtin_nontemporal_store(
-                    0.25 * (((double)ym1 + 2.0 * (double)In[c][q]) + (double)nw[q]),
-                    w.ystar + pt + q * F1);
+                const double ys = 0.25 * (((double)ym1 + 2.0 * (double)In[c][q]) + (double)nw[q]);
+                if (comb) {
+                  // y_out = sum_r c_r y*_r + c_last y*, in ascending N
+                  double v = w.comb->c[0] * pre[0][q];
+#pragma unroll
+                  for (int r = 1; r < COMB_MAX; ++r)
+                    if (r < ncomb) v = v + w.comb->c[r] * pre[r][q];
+                  v = v + w.comb->c_last * ys;
+                  w.comb->yout[w.rhs_off + pt + q * F1] = (T)v;
+                } else {
+                  __builtin_nontemporal_store(ys, w.ystar + pt + q * F1);
+                }
                 if (keep) {
                   w.out_a[pt + q * F1] = ym1;
                   w.out_b[pt + q * F1] = In[c][q];
@@ -343,6 +411,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
               }
             }
           }
+          if (comb && lane_ok && yo + 1 >= ya && yo + 1 < yb) prefetch(yo + 1);
         } else if (e < G) {
 #pragma unroll
           for (int q = 0; q < 3; ++q) W[e][c][q] = nw[q];
@@ -370,12 +439,19 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
 // arguments), blockIdx.z the right-hand side; a workgroup of WPG wavefronts
 // covers one (strip, band), or with WPG = 1 each wavefront of a 4-wave block
 // does.
-template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC, bool KEEP = false>
+template <typename T, int ORDER, int G, bool SKEW1, int WPG, bool VARC, bool KEEP = false,
+          bool COMB = false>
 __global__ __launch_bounds__(WPG > 1 ? 64 * WPG : 256) __attribute__((amdgpu_waves_per_eu(2)))
 void pass2d(const PassArgs<T> a) {
-  const PassSeq<T>& d = a.seq[blockIdx.y];
+  int seq = blockIdx.y, grp = blockIdx.x;
+  if (WPG == 1 && a.order) {
+    const int b = blockIdx.x, xcd = b & 7, k = b >> 3;
+    seq = k % a.nseq;
+    grp = a.order == 1 ? xcd + 8 * (k / a.nseq) : xcd * a.per + k / a.nseq;
+  }
+  const PassSeq<T>& d = a.seq[seq];
   const int unit = WPG > 1 ? (int)blockIdx.x
-                           : __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+                           : __builtin_amdgcn_readfirstlane(grp * 4 + (threadIdx.x >> 6));
   const int strip = unit % a.max_strips;
   const int band = unit / a.max_strips;
   if (strip >= d.strips || band >= a.nbands) return;
@@ -385,8 +461,11 @@ void pass2d(const PassArgs<T> a) {
   w.old = d.old ? d.old + base : nullptr;
   w.out_a = d.out_a + base;
   w.out_b = d.out_b + base;
-  w.ystar = d.ystar + base;
+  w.ystar = d.ystar ? d.ystar + base : nullptr;
   w.c2f = a.c2f;
+  w.f0 = a.f0 ? a.f0 + base : nullptr;
+  w.comb = &a.comb;
+  w.rhs_off = base;
   w.src = a.src_dev;
   w.field = a.g.field;
   w.rhs = blockIdx.z;
@@ -402,7 +481,85 @@ void pass2d(const PassArgs<T> a) {
   w.nsrc = a.g.nsrc;
 #pragma unroll
   for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = d.amp[e];
-  pass_body<T, ORDER, G, SKEW1, WPG, VARC, KEEP>(w, strip, band);
+  pass_body<T, ORDER, G, SKEW1, WPG, VARC, KEEP, COMB>(w, strip, band);
+}
+
+// F_0 = f(t_0, y_0) of the 2-D acoustic operator, with the sources at t_0:
+// the one evaluation all sequences' forward Euler steps share (Sect. 3.6),
+// written to a state-sized buffer for the first passes of the shared form.
+// A 256-thread block covers 64 columns x 4 strips of TY rows; every thread
+// walks down its column keeping the rows y-R..y+R of p and v_y in registers
+// (the y-derivatives); the x-derivatives read the current row.  The same
+// stencil sums, in the same order, as the passes' evaluations.
+template <typename T>
+struct F0Args {
+  const T* y0;
+  T* f0;
+  const T* c2f;
+  const SrcDesc* src;
+  Geometry g;
+  T c2c, invx, invy;
+  double amp;          // source wavelet at t_0
+};
+
+template <typename T, int ORDER, int TY>
+__global__ __launch_bounds__(256) void f0_march2d(const F0Args<T> a) {
+  constexpr int R = Fd<ORDER>::R;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int ntx = (nx + 63) >> 6;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int x = tx * 64 + (threadIdx.x & 63);
+  const int y0 = ty * 4 * TY + (threadIdx.x >> 6) * TY;
+  if (x >= nx || y0 >= ny) return;
+  const int64_t rhs = blockIdx.z;
+  const int64_t base = rhs * a.g.state;
+  const int64_t F1 = a.g.field, F2 = 2 * a.g.field;
+  const T* __restrict__ cp = a.y0 + base;
+  const T* __restrict__ cvx = cp + F1;
+  const T* __restrict__ cvy = cp + F2;
+  T* __restrict__ out = a.f0 + base;
+  T pw[2 * R + 1], vw[2 * R + 1];
+#pragma unroll
+  for (int k = 0; k < 2 * R; ++k) {
+    const int64_t row = (int64_t)wrap(y0 - R + k, ny) * nx + x;
+    pw[k] = cp[row];
+    vw[k] = cvy[row];
+  }
+#pragma unroll
+  for (int i = 0; i < TY; ++i) {
+    const int y = y0 + i;
+    if (y >= ny) break;
+    {
+      const int64_t row = (int64_t)wrap(y + R, ny) * nx + x;
+      pw[2 * R] = cp[row];
+      vw[2 * R] = cvy[row];
+    }
+    const int64_t rowoff = (int64_t)y * nx;
+    T syp = Fd<ORDER>::template w<T>(0) * (pw[R + 1] - pw[R - 1]);
+    T syv = Fd<ORDER>::template w<T>(0) * (vw[R + 1] - vw[R - 1]);
+#pragma unroll
+    for (int k = 1; k < R; ++k) {
+      syp += Fd<ORDER>::template w<T>(k) * (pw[R + 1 + k] - pw[R - 1 - k]);
+      syv += Fd<ORDER>::template w<T>(k) * (vw[R + 1 + k] - vw[R - 1 - k]);
+    }
+    const T sxp = dsum<T, ORDER>(cp + rowoff, x, nx, 1);
+    const T sxv = dsum<T, ORDER>(cvx + rowoff, x, nx, 1);
+    const T c2 = a.c2f ? a.c2f[rowoff + x] : a.c2c;
+    const T dvx = a.invx * sxv;
+    const T dvy = a.invy * syv;
+    const int64_t idx = rowoff + x;
+    T f0 = -(c2 * (dvx + dvy));
+    if (a.g.nsrc) f0 += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
+    out[idx] = f0;
+    out[idx + F1] = -(a.invx * sxp);
+    out[idx + F2] = -(a.invy * syp);
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+      pw[k] = pw[k + 1];
+      vw[k] = vw[k + 1];
+    }
+  }
 }
 
 // A batch of problems: the passes of one round of every (instance, sequence)
@@ -450,6 +607,9 @@ void pass2d_batch(const BatchPassArgs<T> a) {
   w.out_b = it->out_b;
   w.ystar = it->ystar;
   w.c2f = it->c2f;
+  w.f0 = nullptr;
+  w.comb = nullptr;
+  w.rhs_off = 0;
   w.src = nullptr;
   w.field = it->field;
   w.rhs = 0;

@@ -202,6 +202,14 @@ class GBSPlan:
     def set_variant(self, variant):
         B.check(B.lib().gbs_plan_set_variant(self.handle, int(variant)))
 
+    def set_form(self, form):
+        """GBS_FORM_* flags of the blocked passes (gbs_plan_set_form)."""
+        B.check(B.lib().gbs_plan_set_form(self.handle, int(form)))
+
+    def set_wave_order(self, order):
+        """Workgroup order of the blocked passes (gbs_plan_set_wave_order)."""
+        B.check(B.lib().gbs_plan_set_wave_order(self.handle, int(order)))
+
     def autotune(self, y, out=None, macro_steps=5, lanes=0):
         """Times the blocked variants, bands and lane counts
         (gbs_plan_autotune) from ``y`` into ``out`` (a scratch copy if None)

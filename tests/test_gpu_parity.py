@@ -341,3 +341,34 @@ def test_plan_follows_torchs_current_stream():
     back = plan.step(want, n_macro=2)
     assert plan.stream.cuda_stream == torch.cuda.current_stream().cuda_stream
     assert torch.equal(back, got2)
+
+
+@pytest.mark.parametrize("variant", [B.VARIANT_TEMPORAL_S5, B.VARIANT_TEMPORAL])
+@pytest.mark.parametrize("form", [B.FORM_SHARED_F0, B.FORM_FUSED_COMBINE,
+                                  B.FORM_SHARED_F0 | B.FORM_FUSED_COMBINE])
+def test_pass_forms_vs_oracle(form, variant):
+    # f(t0, y0) shared by the first passes (Sect. 3.6) and the combination
+    # folded into the last sequence's final pass: the oracle's values (with
+    # the five sources of the multi-source problem, c^2 field, two
+    # right-hand sides) and the default form's to rounding
+    plan, ops, H, t0 = multi_source_problem()
+    steps, c = oracle_weights(schemes.ORDER8_K6)
+    plan.set_variant(variant)
+    y0 = 1e-3 * np.random.default_rng(25).standard_normal((2, 3) + ops[0].shape)
+    ref = plan.step(to_dev(y0), t0=t0, n_macro=3).cpu().numpy()
+    plan.set_form(form)
+    got = plan.step(to_dev(y0), t0=t0, n_macro=3).cpu().numpy()
+    for r in range(2):
+        want = G.integrate(ops[r], t0, y0[r], H, 3, steps, c)
+        assert rel_err(got[r], want, 0) <= TOL64, r
+    assert rel_err(got, ref, 1) <= 1e-13
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_wave_orders_do_not_change_the_result(order):
+    plan, ops, H, t0 = multi_source_problem()
+    y0 = to_dev(1e-3 * np.random.default_rng(26).standard_normal((2, 3) + ops[0].shape))
+    ref = plan.step(y0, t0=t0, n_macro=2)
+    plan.set_wave_order(order)
+    got = plan.step(y0, t0=t0, n_macro=2)
+    assert torch.equal(got, ref)

@@ -147,15 +147,31 @@ def test_algorithmic_bytes_of_both_schedules():
         v = ctypes.c_int32()
         B.check(B.lib().gbs_plan_get_variant(h, ctypes.byref(v)))
         assert v.value == B.VARIANT_TEMPORAL_S5                  # the 2-D default
+        pts = 64 * 32
+        # the default (at most 5 evaluations per pass): N = 2, 4 take one pass
+        # (write y*), N = 6, 8 two, N = 10, 12 three (2 levels between
+        # passes); round 0 reads y0 once; a combine kernel
+        B.check(B.lib().gbs_plan_algorithmic_bytes(h, *[ctypes.byref(x) for x in out]))
+        assert out[0].value == pts * (24 + 2 * 24 + 2 * (48 + 48 + 24) + 2 * (48 + 96 + 72))
+        assert out[1].value == 3
+        assert out[2].value == pts * (6 * 24 + 24) and out[3].value == 1
+        # f(t0, y0) shared and the combination fused: N = 2, 4 one pass, N = 6,
+        # 8, 10 two, N = 12 three, alone in round 3, where it also forms
+        # y_out from the other five y*; round 0 reads y0 and F_0 once
+        B.check(B.lib().gbs_plan_set_form(h, B.FORM_SHARED_F0 | B.FORM_FUSED_COMBINE))
+        B.check(B.lib().gbs_plan_algorithmic_bytes(h, *[ctypes.byref(x) for x in out]))
+        assert out[0].value == pts * (48 + 2 * 24 + 3 * (48 + 48 + 24)
+                                      + (48 + 48 + 48 + 48 + 5 * 24 + 24))
+        assert out[1].value == 3
+        assert out[2].value == pts * 48 and out[3].value == 1  # f(t0, y0): y0 in, F_0 out
+        B.check(B.lib().gbs_plan_set_form(h, 0))
+        # at most 7 evaluations per pass: N = 2, 4, 6 one pass, N = 8, 10, 12
+        # two; y0, which the six first passes share, counts once
         B.check(B.lib().gbs_plan_set_variant(h, B.VARIANT_TEMPORAL))
         B.check(B.lib().gbs_plan_algorithmic_bytes(h, *[ctypes.byref(x) for x in out]))
-        pts = 64 * 32
-        # temporally blocked, at most 7 evaluations per pass: N = 2, 4, 6 take
-        # one pass (write y*), N = 8, 10, 12 two (2 levels -> y*); y0, which
-        # the six first passes share, counts once
         assert out[0].value == pts * (24 + 3 * 24 + 3 * (48 + 48 + 24))
         assert out[1].value == 2
-        assert out[2].value == pts * (6 * 24 + 24)              # combine
+        assert out[2].value == pts * (6 * 24 + 24) and out[3].value == 1
         B.check(B.lib().gbs_plan_set_variant(h, B.VARIANT_FLAT))
         B.check(B.lib().gbs_plan_algorithmic_bytes(h, *[ctypes.byref(x) for x in out]))
         # streaming: 72 B per stored leap-frog level, last steps 48 B + accumulator
