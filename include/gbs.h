@@ -475,6 +475,26 @@ int gbs_batch_autotune(gbs_batch_plan* plan, void* const* y, int32_t macro_steps
 int gbs_batch_updates_per_macro_step(const gbs_batch_plan* plan, double* updates);
 int gbs_batch_plan_destroy(gbs_batch_plan* plan);
 
+/*
+ * gbs_step_scratch — gbs_step without any device allocation, for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): n_macro macro steps of the problem and
+ * scheme (as for gbs_plan_create, without sources or receivers) from y_in
+ * at t0 into y_out (device, caller-owned; may alias), enqueued on hip_stream.
+ * The workspace is a static device array of the library, GBS_SCRATCH_BYTES
+ * per GPU, held from the first call on a GPU until the process ends; its
+ * address is looked up once per device.  Every call on one GPU uses the same
+ * array and leaves its contents behind: calls that overlap on one GPU (other
+ * threads, other streams without ordering) race.  Nothing in the array needs
+ * clearing (every level is written before it is read).
+ * Errors: those of gbs_plan_create and gbs_step; GBS_ENOMEM when the
+ * problem's workspace (gbs_plan_workspace_bytes) exceeds GBS_SCRATCH_BYTES;
+ * GBS_EUNSUPPORTED for the Fourier derivative.
+ */
+#define GBS_SCRATCH_BYTES ((size_t)64 << 20)
+int gbs_step_scratch(const gbs_problem* prob, const gbs_scheme* sch, double H, double t0,
+                     int32_t n_macro, const void* y_in, void* y_out, void* hip_stream);
+
 /* Message for the last non-zero status returned on this thread. */
 const char* gbs_last_error(void);
 

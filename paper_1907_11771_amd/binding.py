@@ -106,6 +106,7 @@ def lib():
             "gbs_batch_autotune": [vp, P(vp), i32, P(i32), P(i32)],
             "gbs_batch_updates_per_macro_step": [vp, P(dbl)],
             "gbs_batch_plan_destroy": [vp],
+            "gbs_step_scratch": [P(Problem), P(Scheme), dbl, dbl, i32, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)

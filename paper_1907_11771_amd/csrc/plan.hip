@@ -1377,6 +1377,63 @@ extern "C" int gbs_plan_destroy(gbs_plan* P) {
   return GBS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Macro steps without any device allocation (gbs_step_scratch): the plan
+// lives on the host stack and its workspace is `scratch`, a static device
+// array of the library (one copy per GPU, held until the process ends).  In
+// host code `scratch` names a host-side stand-in: its device address comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[GBS_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kScratchDevices] = {};
+
+// The current device's address of `scratch`.
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GBS_EDEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= kScratchDevices) return fail(GBS_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GBS_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return GBS_OK;
+}
+
+}  // namespace
+
+extern "C" int gbs_step_scratch(const gbs_problem* prob, const gbs_scheme* sch, double H,
+                                double t0, int32_t n_macro, const void* y_in, void* y_out,
+                                void* hip_stream) {
+  if (prob && prob->fd_order == GBS_FD_SPECTRAL)
+    return fail(GBS_EUNSUPPORTED, "gbs_step_scratch: the Fourier derivative is not offered");
+  size_t need = 0;
+  int st = gbs_plan_workspace_bytes(prob, sch, &need);
+  if (st) return st;
+  if (need > GBS_SCRATCH_BYTES)
+    return fail(GBS_ENOMEM,
+                "gbs_step_scratch: the problem needs %zu bytes of workspace, the static scratch "
+                "array holds %zu (use gbs_plan_create with a workspace of your own)",
+                need, (size_t)GBS_SCRATCH_BYTES);
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st) return st;
+  gbs_plan P;
+  st = plan_init(&P, prob, sch, H, ws, GBS_SCRATCH_BYTES, hip_stream);
+  if (!st) st = gbs_step(&P, t0, n_macro, y_in, y_out);
+  plan_release(&P);
+  return st;
+}
 
 extern "C" const char* gbs_last_error(void) { return g_last_error.c_str(); }
 
