@@ -302,11 +302,11 @@ def bench_batch(args):
 def bench_adjoint(args):
     """The forward + adjoint workload on its own line (adjoint_leg)."""
     nm = None if args.steps == 500 else args.steps
-    rec = adjoint_leg(nm)
+    rec = adjoint_leg(nm, args.grid or None)
     print(json.dumps(rec), flush=True)
 
 
-def adjoint_leg(n_macro=None):
+def adjoint_leg(n_macro=None, grid=None):
     """Forward + checkpointed adjoint of the receiver misfit (gradients with
     respect to c^2 and p(0)) on the 1024^2 workload: FP64 blocked forward,
     FP32 stepping, and the plain FP64 form; the FP32 gradient's error is
@@ -321,7 +321,8 @@ def adjoint_leg(n_macro=None):
     from synth import fields, workloads
 
     cfg = workloads.CONFIG_ADJOINT
-    n, nm = cfg["n"], cfg["n_macro"] if n_macro is None else n_macro
+    n, nm = grid or cfg["n"], cfg["n_macro"] if n_macro is None else n_macro
+    wname = cfg["name"] if n == cfg["n"] else cfg["name"].replace(str(cfg["n"]), str(n))
     steps, w, _ = scheme_weights(cfg["scheme"])
     dev = torch.device("cuda:0")
     cs = fields.lognormal_speed((n, n), seed=cfg["speed_seed"])
@@ -400,14 +401,14 @@ def adjoint_leg(n_macro=None):
     p64.set_timing(0)
     p64.adjoint_lanes = lanes64
     adj_kernel = "gbs::adj_pass2d<double, 3, true>"
-    prof = measured_traffic(adj_kernel, cfg["name"])
+    prof = measured_traffic(adj_kernel, wname)
     adj_launch_s = adj_ms * 1e-3 / max(adj_n, 1)
     achieved = adj_bytes / max(adj_n, 1) / adj_launch_s / 1e9 if adj_n else None
     upd = n * n * (1 + sum(steps)) * nm
     rec_out = dict(
         metric="fwd+adjoint time at fixed error vs plain", value=(f64 + b64), unit="s",
         higher_is_better=False, n_gpus=1, steps=nm, warmup=1, dtype="f64", data="synthetic",
-        config=dict(workload=cfg["name"], grid=[n, n], macro_steps=nm,
+        config=dict(workload=wname, grid=[n, n], macro_steps=nm,
                     checkpoint_every=cfg["checkpoint_every"], receivers=len(rec)),
         fp64=dict(forward_s=f64, adjoint_s=b64, forward_updates_per_s=upd / f64),
         fp32_stepping=dict(forward_s=f32, adjoint_s=b32,
@@ -469,6 +470,8 @@ def bench_3d(args):
         pl = GBSPlan(B.ACOUSTIC3D, (n, n, n), 8, steps, w, H, fd_order=8, n_rhs=len(rhs),
                      dtype=dtype, c2_field=torch.from_numpy(c2_host).to(dev), c_max=c_top,
                      device=dev)
+        if args.variant:
+            pl.set_variant(args.variant)
         pts = [src["points"][r] for r in rhs]
         pl.set_sources(list(range(len(rhs))), [z * n * n + y * n + x for z, y, x in pts],
                        [src["weight"]] * len(rhs), src["f0"], src["delay"])
@@ -731,6 +734,8 @@ def main():
                     help="stepping precision of the batch workload")
     ap.add_argument("--no-gradient", action="store_true",
                     help="acoustic3d: the forward runs only")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="adjoint1024: another grid size (e.g. 2048 for counter profiles)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="leave out the forward + adjoint leg of the default line")
     ap.add_argument("--summarize-counters", nargs=4,

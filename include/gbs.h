@@ -214,12 +214,12 @@ int gbs_rk4_step(gbs_plan* plan, double t0, int32_t n_steps, double h, const voi
  * the same values in the same order; they differ in work layout only):
  *   GBS_VARIANT_AUTO        library's choice (default): 2-D acoustic
  *                           GBS_VARIANT_TEMPORAL_S5, 3-D acoustic
- *                           GBS_VARIANT_MARCH8, 1-D GBS_VARIANT_FLAT
+ *                           GBS_VARIANT_TILE3D, 1-D GBS_VARIANT_FLAT
  *   GBS_VARIANT_FLAT        one grid point per thread (every operator)
  *   GBS_VARIANT_MARCH8/16   2-D acoustic: each thread marches 8 / 16 rows,
  *                           y-stencil rows kept in registers; 3-D acoustic:
  *                           each thread marches 64 / 128 planes, z-stencil
- *                           planes kept in registers (3-D default: MARCH8)
+ *                           planes kept in registers
  *   GBS_VARIANT_MARCH8/16_NT  as above with non-temporal level stores
  *   GBS_VARIANT_TEMPORAL    2-D acoustic only: temporally blocked passes of
  *                           up to 7 (FD4) / 3 (FD8) evaluations of f per
@@ -235,6 +235,9 @@ int gbs_rk4_step(gbs_plan* plan, double t0, int32_t n_steps, double h, const voi
  *                           wavefronts of a workgroup sharing their edge
  *                           columns through LDS (halo recomputed only at
  *                           the workgroup's edges)
+ *   GBS_VARIANT_TILE3D      3-D acoustic only: z-marching sweeps in which a
+ *                           1024-thread block stages each plane's 64 x 16
+ *                           tile and its x/y halo in LDS once
  * The temporally blocked variants agree with the streaming ones to
  * rounding (the combination is summed in the same order, the products may
  * be contracted differently).
@@ -257,7 +260,8 @@ enum {
   GBS_VARIANT_TEMPORAL_S6 = 9,
   GBS_VARIANT_PLAIN = 10,
   GBS_VARIANT_TEMPORAL_WG4 = 11,
-  GBS_VARIANT_TEMPORAL_WG8 = 12
+  GBS_VARIANT_TEMPORAL_WG8 = 12,
+  GBS_VARIANT_TILE3D = 13
 };
 int gbs_plan_set_variant(gbs_plan* plan, int32_t variant);
 int gbs_plan_set_band(gbs_plan* plan, int32_t rows);

@@ -22,6 +22,7 @@ VARIANT_MARCH8_NT, VARIANT_MARCH16_NT = 4, 5
 VARIANT_TEMPORAL, VARIANT_TEMPORAL4, VARIANT_TEMPORAL_S5, VARIANT_TEMPORAL_S6 = 6, 7, 8, 9
 VARIANT_PLAIN = 10
 VARIANT_TEMPORAL_WG4, VARIANT_TEMPORAL_WG8 = 11, 12
+VARIANT_TILE3D = 13
 FORM_SHARED_F0, FORM_FUSED_COMBINE = 1, 2
 MAX_SEQ = 16
 MAX_SRC = 16

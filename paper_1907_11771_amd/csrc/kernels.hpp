@@ -317,6 +317,203 @@ __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
   }
 }
 
+// 3-D acoustic sweeps with the x/y neighbourhood of every plane staged in
+// LDS.  A 1024-thread block covers a 64 x 16 tile of (x, y) columns and
+// marches up TZ planes; every thread keeps the planes z-R..z+R of p and v_z
+// of its column in registers (the z-derivatives).  Per plane the block
+// writes p, v_x and v_y of its tile, with the R-wide halo of p and v_x along
+// x and of p and v_y along y, to LDS once (two buffers, one barrier per
+// plane), and the x- and y-derivatives read LDS: a value of the plane is
+// fetched from L2/HBM once per block that needs it (1.25 halo values per
+// tile point) instead of once per thread that needs it.  Columns and rows
+// past a ragged edge hold the periodic continuation, so every valid column
+// sees its true neighbours.  Same stencil sums, in the same order, as
+// eval_rhs.  `point(idx, dvx, dvy, dvz, f, c)` receives, for every valid
+// column, the flat index, the velocity derivatives, f_v (f[1..3]) and the
+// plane's four values.  (Loading the point's other inputs a plane ahead
+// needs registers that make the sweep spill.)
+template <typename T, int ORDER, int TZ, typename Point>
+__device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geometry& g,
+                                             T invx, T invy, T invz, Point point) {
+  constexpr int R = Fd<ORDER>::R;
+  constexpr int BX = 64, BY = 16, LX = BX + 2 * R, LY = BY + 2 * R;
+  constexpr int NYH = 2 * R * BX * 2;          // y-halo values (p, v_y) per plane
+  constexpr int NXH = BY * 2 * R * 2;          // x-halo values (p, v_x) per plane
+  static_assert(NYH <= 1024 && NXH <= 1024, "halo larger than the block");
+  __shared__ T sp[2][LY][LX];
+  __shared__ T svx[2][BY][LX];
+  __shared__ T svy[2][LY][BX];
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ntx = (nx + BX - 1) / BX, nty = (ny + BY - 1) / BY;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
+  const int x0 = tx * BX, y0 = ty * BY, z0 = tz * TZ;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool valid = x < nx && y < ny;
+  const int64_t F1 = g.field;
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t own = (int64_t)pmod(y, ny) * nx + pmod(x, nx);   // column within a plane
+  const T* __restrict__ cvx = cp + F1;
+  const T* __restrict__ cvy = cp + 2 * F1;
+  const T* __restrict__ cvz = cp + 3 * F1;
+  // this thread's halo values: one of the y-halo (field yf, LDS row yr, column
+  // yc) and, for the first NXH threads, one of the x-halo
+  const bool hy = t < NYH, hx = t < NXH;
+  int yr = 0, yc = 0, xr = 0, xc = 0;
+  int64_t ycol = 0, xcol = 0;
+  const T* ysrc = cp;
+  const T* xsrc = cp;
+  if (hy) {
+    const int f = t / (2 * R * BX), pos = t % (2 * R * BX), hr = pos / BX;
+    yc = pos % BX;
+    yr = hr < R ? hr : BY + hr;                               // LDS row (0..R-1, BY+R..)
+    ycol = (int64_t)pmod(y0 + yr - R, ny) * nx + pmod(x0 + yc, nx);
+    ysrc = f == 0 ? cp : cvy;
+  }
+  if (hx) {
+    const int f = t / (BY * 2 * R), pos = t % (BY * 2 * R), hc = pos % (2 * R);
+    xr = pos / (2 * R);
+    xc = hc < R ? hc : BX + hc;                               // LDS column
+    xcol = (int64_t)pmod(y0 + xr, ny) * nx + pmod(x0 + xc - R, nx);
+    xsrc = f == 0 ? cp : cvx;
+  }
+  const bool yp = hy && t < NYH / 2, xp = hx && t < NXH / 2;  // halo of p (else v_y / v_x)
+  T pw[2 * R + 1], vw[2 * R + 1];
+#pragma unroll
+  for (int k = 0; k <= 2 * R; ++k) {
+    const int64_t e = (int64_t)pmod(z0 - R + k, nz) * plane + own;
+    pw[k] = cp[e];
+    vw[k] = cvz[e];
+  }
+  const int zend = min(z0 + TZ, nz);
+  const int64_t pil = (int64_t)y * nx + x;         // valid columns only
+  T vxo, vyo, hyv = T(0), hxv = T(0);
+  {
+    const int64_t zo = (int64_t)z0 * plane;
+    vxo = cvx[zo + own];
+    vyo = cvy[zo + own];
+    if (hy) hyv = ysrc[zo + ycol];
+    if (hx) hxv = xsrc[zo + xcol];
+  }
+  for (int z = z0; z < zend; ++z) {
+    const int b = z & 1;
+    sp[b][ly + R][lx + R] = pw[R];
+    svx[b][ly][lx + R] = vxo;
+    svy[b][ly + R][lx] = vyo;
+    if (hy) {
+      if (yp) sp[b][yr][yc + R] = hyv;
+      else svy[b][yr][yc] = hyv;
+    }
+    if (hx) {
+      if (xp) sp[b][xr + R][xc] = hxv;
+      else svx[b][xr][xc] = hxv;
+    }
+    const T cvxc = vxo, cvyc = vyo;
+    __syncthreads();
+    // the next plane's stencil values, in flight while this plane is evaluated
+    T pnext = T(0), vnext = T(0);
+    if (z + 1 < zend) {
+      const int64_t zn = (int64_t)(z + 1) * plane;
+      const int64_t e = (int64_t)pmod(z + 1 + R, nz) * plane + own;
+      pnext = cp[e];
+      vnext = cvz[e];
+      vxo = cvx[zn + own];
+      vyo = cvy[zn + own];
+      if (hy) hyv = ysrc[zn + ycol];
+      if (hx) hxv = xsrc[zn + xcol];
+    }
+    T sxp = T(0), syp = T(0), sxv = T(0), syv = T(0), szp = T(0), szv = T(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const T w = Fd<ORDER>::template w<T>(k);
+      sxv += w * (svx[b][ly][lx + R + k + 1] - svx[b][ly][lx + R - k - 1]);
+      syv += w * (svy[b][ly + R + k + 1][lx] - svy[b][ly + R - k - 1][lx]);
+      sxp += w * (sp[b][ly + R][lx + R + k + 1] - sp[b][ly + R][lx + R - k - 1]);
+      syp += w * (sp[b][ly + R + k + 1][lx + R] - sp[b][ly + R - k - 1][lx + R]);
+      szp += w * (pw[R + 1 + k] - pw[R - 1 - k]);
+      szv += w * (vw[R + 1 + k] - vw[R - 1 - k]);
+    }
+    if (valid) {
+      const T dvx = invx * sxv;
+      const T dvy = invy * syv;
+      const T dvz = invz * szv;
+      T f[4], c[4] = {pw[R], cvxc, cvyc, vw[R]};
+      f[1] = -(invx * sxp);
+      f[2] = -(invy * syp);
+      f[3] = -(invz * szp);
+      point((int64_t)z * plane + pil, dvx, dvy, dvz, f, c);
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+      pw[k] = pw[k + 1];
+      vw[k] = vw[k + 1];
+    }
+    pw[2 * R] = pnext;
+    vw[2 * R] = vnext;
+  }
+}
+
+// Two blocks per CU (8 waves per SIMD) need at most 64 VGPRs: asked for in
+// FP32, where the sweep fits them; FP64 runs one block per CU.
+template <typename T>
+constexpr int tile3d_waves() { return sizeof(T) == 4 ? 8 : 4; }
+
+template <typename T, int ORDER, int TZ>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(tile3d_waves<T>())))
+void lf_tile3d(const StepArgs<T> a) {
+  const SeqDesc<T>& d = a.seq[blockIdx.y];
+  const int64_t rhs = blockIdx.z;
+  const int64_t base = rhs * a.g.state;
+  const int64_t F1 = a.g.field;
+  tile3d_march<T, ORDER, TZ>(
+      d.cur + base, a.g, a.invx, a.invy, a.invz,
+      [&](int64_t idx, T dvx, T dvy, T dvz, T* f, const T* c) {
+        const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
+        f[0] = -(c2 * ((dvx + dvy) + dvz));
+        if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t e = base + q * F1 + idx;
+          const T o = d.old[e];
+          const T nw = o + d.h2 * f[q];
+          if (!(d.mode & MODE_LAST)) {
+            // read back only by the next launch, after the whole grid
+            __builtin_nontemporal_store(nw, d.out + e);
+          } else {
+            const double ys = 0.25 * (((double)o + 2.0 * (double)c[q]) + (double)nw);
+            double v = d.cw * ys;
+            if (!(d.mode & MODE_FIRST)) v = a.acc[e] + v;
+            if (d.mode & MODE_FINAL) a.yout[e] = (T)v;
+            else a.acc[e] = v;
+          }
+        }
+      });
+}
+
+// The shared first evaluation and the forward-Euler steps of every
+// sequence in the LDS-tiled layout of lf_tile3d.
+template <typename T, int ORDER, int TZ>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(tile3d_waves<T>())))
+void first_tile3d(const FirstArgs<T> a) {
+  const int64_t rhs = blockIdx.z;
+  const int64_t base = rhs * a.g.state;
+  const int64_t F1 = a.g.field;
+  tile3d_march<T, ORDER, TZ>(
+      a.y0 + base, a.g, a.invx, a.invy, a.invz,
+      [&](int64_t idx, T dvx, T dvy, T dvz, T* f, const T* c) {
+        const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
+        f[0] = -(c2 * ((dvx + dvy) + dvz));
+        if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t fo = base + q * F1;
+          for (int j = 0; j < a.nseq; ++j)
+            __builtin_nontemporal_store(c[q] + a.h[j] * f[q], a.out[j] + fo + idx);
+        }
+      });
+}
+
 // The shared first evaluation and the forward-Euler steps of every
 // sequence, 3-D, in the z-marching layout of lf_march3d.  Same arithmetic,
 // in the same order, as first_kernel.

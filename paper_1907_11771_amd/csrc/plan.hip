@@ -334,9 +334,9 @@ void fill_geometry(const gbs_plan* P, Geometry& g, T& c2c, const T*& c2f, T& ix,
 int resolve_variant(const gbs_plan* P) {
   if (P->variant != GBS_VARIANT_AUTO) return P->variant;
   if (P->prob.op == GBS_ACOUSTIC2D) return GBS_VARIANT_TEMPORAL_S5;
-  // the z-marching kernels index a field with 32-bit element offsets
+  // the z-marching adjoint sweeps index a field with 32-bit element offsets
   if (P->prob.op == GBS_ACOUSTIC3D)
-    return P->field < (int64_t(1) << 31) ? GBS_VARIANT_MARCH8 : GBS_VARIANT_FLAT;
+    return P->field < (int64_t(1) << 31) ? GBS_VARIANT_TILE3D : GBS_VARIANT_FLAT;
   return GBS_VARIANT_FLAT;
 }
 
@@ -720,8 +720,25 @@ void launch_march3d(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gz) {
                      0, P->stream, sa);
 }
 
+// LDS-tiled 3-D sweeps: 64 x 16 columns per 1024-thread block, TILE_TZ planes
+constexpr int TILE_TZ = 128;
+
+unsigned tile3d_blocks(const gbs_plan* P) {
+  const int ntx = (int)((P->prob.n[0] + 63) / 64);
+  const int nty = (int)((P->prob.n[1] + 15) / 16);
+  const int ntz = (int)((P->prob.n[2] + TILE_TZ - 1) / TILE_TZ);
+  return (unsigned)(ntx * nty * ntz);
+}
+
 template <typename T, int ORDER, int OP>
 void launch_first(gbs_plan* P, const FirstArgs<T>& fa, unsigned gx, unsigned gz) {
+  if constexpr (OP == OP_AC3D && ORDER != GBS_FD_SPECTRAL) {
+    if (resolve_variant(P) == GBS_VARIANT_TILE3D) {
+      hipLaunchKernelGGL((first_tile3d<T, ORDER, TILE_TZ>), dim3(tile3d_blocks(P), 1, gz),
+                         dim3(1024), 0, P->stream, fa);
+      return;
+    }
+  }
   if constexpr (OP == OP_AC3D) {
     const int v = resolve_variant(P);
     if (v == GBS_VARIANT_MARCH8 || v == GBS_VARIANT_MARCH16) {
@@ -738,6 +755,13 @@ void launch_first(gbs_plan* P, const FirstArgs<T>& fa, unsigned gx, unsigned gz)
 
 template <typename T, int ORDER, int OP>
 void launch_lf(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gx, unsigned gz) {
+  if constexpr (OP == OP_AC3D && ORDER != GBS_FD_SPECTRAL) {
+    if (resolve_variant(P) == GBS_VARIANT_TILE3D) {
+      hipLaunchKernelGGL((lf_tile3d<T, ORDER, TILE_TZ>), dim3(tile3d_blocks(P), n, gz),
+                         dim3(1024), 0, P->stream, sa);
+      return;
+    }
+  }
   if constexpr (OP == OP_AC3D) {
     switch (resolve_variant(P)) {
       case GBS_VARIANT_MARCH8: launch_march3d<T, ORDER, 64>(P, sa, n, gz); return;
@@ -1076,14 +1100,17 @@ extern "C" int gbs_rk4_step(gbs_plan* P, double t0, int32_t n_steps, double h, c
 
 extern "C" int gbs_plan_set_variant(gbs_plan* P, int32_t variant) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
-  if (variant < GBS_VARIANT_AUTO || variant > GBS_VARIANT_TEMPORAL_WG8)
+  if (variant < GBS_VARIANT_AUTO || variant > GBS_VARIANT_TILE3D)
     return fail(GBS_EINVAL, "unknown variant %d", variant);
+  if (variant == GBS_VARIANT_TILE3D && P->prob.op != GBS_ACOUSTIC3D)
+    return fail(GBS_EUNSUPPORTED, "GBS_VARIANT_TILE3D is built for the 3-D operator only");
   const bool march3d = P->prob.op == GBS_ACOUSTIC3D &&
-                       (variant == GBS_VARIANT_MARCH8 || variant == GBS_VARIANT_MARCH16);
+                       (variant == GBS_VARIANT_MARCH8 || variant == GBS_VARIANT_MARCH16 ||
+                        variant == GBS_VARIANT_TILE3D);
   if (march3d && P->field >= (int64_t(1) << 31))
     return fail(GBS_EUNSUPPORTED, "the 3-D marching kernels need fields of fewer than 2^31 points");
-  if (variant >= GBS_VARIANT_MARCH8 && variant != GBS_VARIANT_PLAIN && !march3d &&
-      P->prob.op != GBS_ACOUSTIC2D)
+  if (variant >= GBS_VARIANT_MARCH8 && variant != GBS_VARIANT_PLAIN &&
+      variant != GBS_VARIANT_TILE3D && !march3d && P->prob.op != GBS_ACOUSTIC2D)
     return fail(GBS_EUNSUPPORTED, "this variant is not built for this operator");
   P->variant = variant;
   return GBS_OK;
@@ -2242,7 +2269,8 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
   hipStream_t s = P->stream;
   // the 3-D operator's z-marching sweeps unless a flat form is chosen
   const int v = resolve_variant(P);
-  const bool march = OP == OP_AC3D && (v == GBS_VARIANT_MARCH8 || v == GBS_VARIANT_MARCH16);
+  const bool march = OP == OP_AC3D && (v == GBS_VARIANT_MARCH8 || v == GBS_VARIANT_MARCH16 ||
+                                      v == GBS_VARIANT_TILE3D);
   const unsigned mblocks = (unsigned)(((P->prob.n[0] + 63) / 64) * ((P->prob.n[1] + 3) / 4) *
                                       ((P->prob.n[2] + 63) / 64));
 

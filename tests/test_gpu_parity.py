@@ -76,7 +76,8 @@ def test_acoustic2d_variable_c2_with_source_vs_oracle():
         assert rel_err(got[q], want[q], None) <= TOL64, q
 
 
-def test_acoustic3d_fd8_variable_c2_multi_rhs_vs_oracle():
+@pytest.mark.parametrize("variant", [B.VARIANT_AUTO, B.VARIANT_TILE3D])
+def test_acoustic3d_fd8_variable_c2_multi_rhs_vs_oracle(variant):
     shape = (12, 20, 24)   # z, y, x
     sch = schemes.ORDER8_K6
     steps, c = oracle_weights(sch)
@@ -91,6 +92,7 @@ def test_acoustic3d_fd8_variable_c2_multi_rhs_vs_oracle():
     flat = [z * 20 * 24 + y * 24 + x for _, (z, y, x) in srcs]
     f0, delay = 30.0, 0.05
     plan.set_sources([0, 1], flat, [50.0, -20.0], f0, delay)
+    plan.set_variant(variant)
     out = plan.step(to_dev(y0), n_macro=3)
     got = out.cpu().numpy()
     for r, (w_, (idx)) in enumerate(zip([50.0, -20.0], [srcs[0][1], srcs[1][1]])):
@@ -372,3 +374,38 @@ def test_wave_orders_do_not_change_the_result(order):
     plan.set_wave_order(order)
     got = plan.step(y0, t0=t0, n_macro=2)
     assert torch.equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(70, 22, 90), (64, 32, 128), (9, 9, 9)])
+def test_tile3d_matches_flat_and_oracle(dtype, shape):
+    # the LDS-tiled 3-D sweeps against the one-point-per-thread ones (the same
+    # stencil sums; products may contract differently) and, for the ragged
+    # grid, against the oracle; ragged tiles in x, y and z, and the smallest
+    # grid FD8 allows, smaller than one tile
+    nz, ny, nx = shape
+    cs = fields.lognormal_speed(shape, seed=27)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(shape), 3,
+                           workloads.SIGMA_FD8)
+    y0 = np.random.default_rng(28).standard_normal((2, 4) + shape)
+    srcs = [(0, (nz // 2, ny // 3, nx // 4), 1e3), (1, (0, 0, 7), -5e2)]
+    outs = []
+    for v in (B.VARIANT_FLAT, B.VARIANT_TILE3D):
+        plan = lib_plan(B.ACOUSTIC3D, (nx, ny, nz), schemes.ORDER8_K6, H, fd_order=8, n_rhs=2,
+                        dtype=dtype, c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()),
+                        check_stability=False)
+        plan.set_sources([r for r, _, _ in srcs], [(z * ny + y) * nx + x for _, (z, y, x), _ in srcs],
+                         [w for _, _, w in srcs], 25.0, 0.004)
+        plan.set_variant(v)
+        outs.append(plan.step(to_dev(y0, dtype), t0=0.003, n_macro=2).double().cpu().numpy())
+    e = rel_err(outs[1], outs[0], 1)
+    print(shape, dtype, "tile3d vs flat", e)
+    assert e <= (1e-13 if dtype == torch.float64 else 2e-6)
+    if shape == (70, 22, 90):
+        steps, c = oracle_weights(schemes.ORDER8_K6)
+        for r, idx, w in srcs:
+            op = OP.Acoustic(shape, c2=cs ** 2, r=4, sources=[OP.Source(idx, 25.0, 0.004, w)])
+            want = G.integrate(op, 0.003, y0[r], H, 2, steps, c)
+            e = rel_err(outs[1][r], want, 0)
+            print("tile3d vs oracle, rhs", r, e)
+            assert e <= (TOL64 if dtype == torch.float64 else 3e-5)

@@ -220,11 +220,19 @@ def test_3d_variants_on_host():
     try:
         v = ctypes.c_int32()
         B.check(B.lib().gbs_plan_get_variant(h, ctypes.byref(v)))
-        assert v.value == B.VARIANT_MARCH8                      # z-marching by default
-        for ok in (B.VARIANT_FLAT, B.VARIANT_MARCH8, B.VARIANT_MARCH16, B.VARIANT_PLAIN):
+        assert v.value == B.VARIANT_TILE3D                      # LDS-tiled by default
+        for ok in (B.VARIANT_FLAT, B.VARIANT_MARCH8, B.VARIANT_MARCH16, B.VARIANT_PLAIN,
+                   B.VARIANT_TILE3D):
             B.check(B.lib().gbs_plan_set_variant(h, ok))
         for bad in (B.VARIANT_MARCH8_NT, B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL_WG4):
             assert B.lib().gbs_plan_set_variant(h, bad) == B.GBS_EUNSUPPORTED
+    finally:
+        B.plan_destroy(h)
+    pr = B.make_problem(B.ACOUSTIC2D, (64, 64))
+    h = B.plan_create(pr, sc, 1e-4, FAKE_WS, B.workspace_bytes(pr, sc))
+    try:
+        assert B.lib().gbs_plan_set_variant(h, B.VARIANT_TILE3D) == B.GBS_EUNSUPPORTED
+        assert B.lib().gbs_plan_set_variant(h, 14) == B.GBS_EINVAL
     finally:
         B.plan_destroy(h)
 
