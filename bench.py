@@ -736,6 +736,8 @@ def main():
                     help="acoustic3d: the forward runs only")
     ap.add_argument("--grid", type=int, default=0,
                     help="adjoint1024: another grid size (e.g. 2048 for counter profiles)")
+    ap.add_argument("--no-lanes", action="store_true",
+                    help="leave out the lanes-tuned timing of the default line")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="leave out the forward + adjoint leg of the default line")
     ap.add_argument("--summarize-counters", nargs=4,
@@ -798,9 +800,11 @@ def main():
         if args.band:
             B.check(B.lib().gbs_plan_set_band(plan.handle, args.band))
     else:
-        # the library's own autotuner picks the blocked variant, band and
-        # lane count (untimed; it writes only into `out`)
-        tuned = plan.autotune(y, out, macro_steps=5, lanes=0)
+        # the library's own autotuner picks the blocked variant and band
+        # (untimed; it writes only into `out`).  One lane: the passes of a
+        # macro step run one launch at a time, so that each launch's HIP-event
+        # duration (the roofline figure) belongs to the form that is timed.
+        tuned = plan.autotune(y, out, macro_steps=5, lanes=1)
 
     if args.wave_order is not None:
         B.check(B.lib().gbs_plan_set_wave_order(plan.handle, args.wave_order))
@@ -813,11 +817,8 @@ def main():
     plan.step(y, out, n_macro=args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    # the roofline: the same K steps on one lane (one launch at a time, so
-    # that each launch's HIP-event duration is its own), every launch
-    # bracketed by HIP events on the plan's stream (created beforehand)
-    lanes_tuned = plan.lanes
-    plan.set_lanes(1)
+    # the roofline: the same K steps with every launch bracketed by HIP
+    # events on the plan's stream (created beforehand)
     plan.set_timing(max(args.steps, 2))
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -826,7 +827,22 @@ def main():
     dt_events = time.perf_counter() - t
     step_ms, step_n, aux_ms, aux_n = plan.get_timing()
     plan.set_timing(0)
-    plan.set_lanes(lanes_tuned)
+    lanes_alt = None
+    if tuned is not None and not args.no_lanes:
+        # for information: the form the autotuner picks when it may also
+        # spread the passes over several streams (overlapping launches, so
+        # no per-launch roofline)
+        alt = GBSPlan(B.ACOUSTIC2D, (n, n), cfg["scheme"]["p"], steps, w, cfg["H"], fd_order=4,
+                      dtype=torch.float64, c2=cfg["c2"], device=dev)
+        tl = alt.autotune(y, out, macro_steps=5, lanes=0)
+        alt.step(y, out, n_macro=args.warmup)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        alt.step(y, out, n_macro=args.steps)
+        torch.cuda.synchronize()
+        lanes_alt = dict(variant=tl[0], band=tl[1], lanes=tl[2],
+                         ms_per_step=(time.perf_counter() - t) * 1e3 / args.steps)
+        del alt
 
     variant = plan.variant()
     kstep, kaux = kernel_names(variant, B)
@@ -862,7 +878,8 @@ def main():
         streaming_equivalent=dict(bytes_per_update=STREAM_BYTES_PER_UPDATE,
                                   gbps=upd * STREAM_BYTES_PER_UPDATE / dt / 1e9,
                                   frac=upd * STREAM_BYTES_PER_UPDATE / dt / 1e9 / HBM_PEAK_GBS),
-        ms_per_step_one_lane_with_events=dt_events * 1e3 / args.steps,
+        ms_per_step_with_events=dt_events * 1e3 / args.steps,
+        tuned_with_lanes=lanes_alt,
         aux_kernel=dict(kernel=kaux, avg_launch_us=aux_ms * 1e3 / max(aux_n, 1),
                         gbps=ab * args.steps / (aux_ms * 1e-3) / 1e9 if aux_ms else None),
     )

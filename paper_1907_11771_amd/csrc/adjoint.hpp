@@ -313,6 +313,223 @@ void adj_march3d(const AdjArgs<T> a) {
   }
 }
 
+// The sweeps of adj_march3d in the LDS-tiled layout of lf_tile3d: a block
+// of 64 x BY threads covers 64 x BY columns and marches up TZ planes, the
+// right-hand sides one after another (so the c^2 gradient of a point keeps
+// one writer).  Per plane the block stages c^2 u_p (x and y halo), u_x (x
+// halo), u_y (y halo) and, for the gradient (GRAD), the level's v_x (x) and
+// v_y (y) in LDS once (two buffers, one barrier per plane); the z-windows
+// of c^2 u_p, u_z and the level's v_z stay in registers.  Columns past a
+// ragged edge hold the periodic continuation.  Same products and sums, in
+// the same order, as adj_march3d.  Fields of fewer than 2^31 points.
+template <typename T, int ORDER, int TZ, int BY, bool FIRST, bool GRAD, int WPE>
+__global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE)))
+void adj_tile3d(const AdjArgs<T> a) {
+  constexpr int R = Fd<ORDER>::R;
+  constexpr int BX = 64, LX = BX + 2 * R, LY = BY + 2 * R, NT = 64 * BY;
+  constexpr int NF = GRAD ? 3 : 2;         // staged fields with a y (x) halo
+  constexpr int NYP = 2 * R * BX;          // y-halo positions per staged field
+  constexpr int NXP = BY * 2 * R;          // x-halo positions per staged field
+  constexpr int NYI = (NF * NYP + NT - 1) / NT;   // y-halo items per thread
+  static_assert(NF * NXP <= NT, "x halo larger than the block");
+  __shared__ T scu[2][LY][LX];             // c^2 u_p
+  __shared__ T sux[2][BY][LX];
+  __shared__ T suy[2][LY][BX];
+  __shared__ T slx[GRAD ? 2 : 1][GRAD ? BY : 1][GRAD ? LX : 1];   // level v_x, v_y
+  __shared__ T sly[GRAD ? 2 : 1][GRAD ? LY : 1][GRAD ? BX : 1];
+  const uint32_t nx = a.g.nx, ny = a.g.ny;
+  const int nz = a.g.nz;
+  const int ntx = (int)((nx + BX - 1) / BX), nty = (int)((ny + BY - 1) / BY);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
+  const int x0 = tx * BX, y0 = ty * BY, z0 = tz * TZ;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool valid = x < (int)nx && y < (int)ny;
+  const uint32_t F1 = (uint32_t)a.g.field;
+  const uint32_t plane = nx * ny;
+  const uint32_t own = (uint32_t)pmod(y, ny) * nx + (uint32_t)pmod(x, nx);
+  const uint32_t pil = (uint32_t)y * nx + (uint32_t)x;
+  const int zend = min(z0 + TZ, nz);
+  const T h2 = (T)(2.0 * a.h);
+  const T cq = (T)(0.25 * a.cw), ch = (T)(0.5 * a.cw);
+  const T* __restrict__ c2f = a.c2f;
+  // halo items: y-halo items t + NT i (field 0 c^2 u_p, 1 u_y, 2 level v_y),
+  // x-halo item t (field 0 c^2 u_p, 1 u_x, 2 level v_x); position -> column
+  auto ycol = [&](int it) {
+    const int pos = it % NYP, hr = pos / BX;
+    return (uint32_t)pmod(y0 + (hr < R ? hr : BY + hr) - R, ny) * nx +
+           (uint32_t)pmod(x0 + pos % BX, nx);
+  };
+  const bool hx = t < NF * NXP;
+  const int xf = t / NXP, xpos = t % NXP, xhc = xpos % (2 * R);
+  const int xr = xpos / (2 * R), xc = xhc < R ? xhc : BX + xhc;
+  const uint32_t xcol = (uint32_t)pmod(y0 + xr, ny) * nx + (uint32_t)pmod(x0 + xc - R, nx);
+  int zb = 0;                              // planes marched so far (buffer parity)
+  for (int r = 0; r < a.nrhs; ++r) {
+    const int64_t base = (int64_t)r * a.g.state;
+    const T* __restrict__ up = (FIRST ? a.ybar : a.P) + base;     // u_p
+    const T* __restrict__ ux = up + F1;
+    const T* __restrict__ uy = up + 2 * (int64_t)F1;
+    const T* __restrict__ uz = up + 3 * (int64_t)F1;
+    const T* __restrict__ lvx = a.level + base + F1;
+    const T* __restrict__ lvy = lvx + F1;
+    const T* __restrict__ lvz = lvy + F1;
+    auto cu = [&](uint32_t e) { return (c2f ? c2f[e] : a.c2c) * up[e]; };
+    auto yhalo = [&](int it, uint32_t zo) -> T {
+      const int f = it / NYP;
+      const uint32_t e = zo + ycol(it);
+      return f == 0 ? cu(e) : (f == 1 ? uy[e] : lvy[e]);
+    };
+    auto xhalo = [&](uint32_t zo) -> T {
+      const uint32_t e = zo + xcol;
+      return xf == 0 ? cu(e) : (xf == 1 ? ux[e] : lvx[e]);
+    };
+    T qa[2 * R + 1], qb[2 * R + 1], ql[GRAD ? 2 * R + 1 : 1];
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) {
+      const uint32_t e = (uint32_t)pmod(z0 - R + k, nz) * plane + own;
+      qa[k] = cu(e);
+      qb[k] = uz[e];
+      if constexpr (GRAD) ql[k] = lvz[e];
+    }
+    T oux, ouy, olx = T(0), oly = T(0), hyv[NYI], hxv = T(0);
+    {
+      const uint32_t zo = (uint32_t)z0 * plane;
+      oux = ux[zo + own];
+      ouy = uy[zo + own];
+      if constexpr (GRAD) {
+        olx = lvx[zo + own];
+        oly = lvy[zo + own];
+      }
+#pragma unroll
+      for (int i = 0; i < NYI; ++i)
+        if (t + NT * i < NF * NYP) hyv[i] = yhalo(t + NT * i, zo);
+      if (hx) hxv = xhalo(zo);
+    }
+    for (int z = z0; z < zend; ++z, ++zb) {
+      const int b = zb & 1;
+      scu[b][ly + R][lx + R] = qa[R];
+      sux[b][ly][lx + R] = oux;
+      suy[b][ly + R][lx] = ouy;
+      if constexpr (GRAD) {
+        slx[b][ly][lx + R] = olx;
+        sly[b][ly + R][lx] = oly;
+      }
+#pragma unroll
+      for (int i = 0; i < NYI; ++i) {
+        const int it = t + NT * i;
+        if (it >= NF * NYP) continue;
+        const int f = it / NYP, pos = it % NYP, hr = pos / BX, c = pos % BX;
+        const int row = hr < R ? hr : BY + hr;
+        if (f == 0) scu[b][row][c + R] = hyv[i];
+        else if (f == 1) suy[b][row][c] = hyv[i];
+        else if constexpr (GRAD) sly[b][row][c] = hyv[i];
+      }
+      if (hx) {
+        if (xf == 0) scu[b][xr + R][xc] = hxv;
+        else if (xf == 1) sux[b][xr][xc] = hxv;
+        else if constexpr (GRAD) slx[b][xr][xc] = hxv;
+      }
+      __syncthreads();
+      // the next plane's values, in flight while this plane is evaluated
+      T anext = T(0), bnext = T(0), lnext = T(0);
+      if (z + 1 < zend) {
+        const uint32_t zn = (uint32_t)(z + 1) * plane;
+        const uint32_t e = (uint32_t)pmod(z + 1 + R, nz) * plane + own;
+        anext = cu(e);
+        bnext = uz[e];
+        if constexpr (GRAD) lnext = lvz[e];
+        oux = ux[zn + own];
+        ouy = uy[zn + own];
+        if constexpr (GRAD) {
+          olx = lvx[zn + own];
+          oly = lvy[zn + own];
+        }
+#pragma unroll
+        for (int i = 0; i < NYI; ++i)
+          if (t + NT * i < NF * NYP) hyv[i] = yhalo(t + NT * i, zn);
+        if (hx) hxv = xhalo(zn);
+      }
+      T sb = T(0), sa = T(0), dxx = T(0), dyy = T(0), cx = T(0), cy = T(0);
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const T w = Fd<ORDER>::template w<T>(k);
+        sb += w * (qb[R + 1 + k] - qb[R - 1 - k]);
+        sa += w * (qa[R + 1 + k] - qa[R - 1 - k]);
+        dxx += w * (sux[b][ly][lx + R + k + 1] - sux[b][ly][lx + R - k - 1]);
+        dyy += w * (suy[b][ly + R + k + 1][lx] - suy[b][ly + R - k - 1][lx]);
+        cx += w * (scu[b][ly + R][lx + R + k + 1] - scu[b][ly + R][lx + R - k - 1]);
+        cy += w * (scu[b][ly + R + k + 1][lx + R] - scu[b][ly + R - k - 1][lx + R]);
+      }
+      T at[4];
+      at[0] = a.invx * dxx + a.invy * dyy;
+      at[1] = a.invx * cx;
+      at[2] = a.invy * cy;
+      at[0] += a.invz * sb;
+      at[3] = a.invz * sa;
+      T dv = T(0);
+      if constexpr (GRAD) {
+        T sl = T(0), gx = T(0), gy = T(0);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const T w = Fd<ORDER>::template w<T>(k);
+          sl += w * (ql[R + 1 + k] - ql[R - 1 - k]);
+          gx += w * (slx[b][ly][lx + R + k + 1] - slx[b][ly][lx + R - k - 1]);
+          gy += w * (sly[b][ly + R + k + 1][lx] - sly[b][ly + R - k - 1][lx]);
+        }
+        T dd = a.invx * gx + a.invy * gy;
+        dd += a.invz * sl;
+        dv = -dd;
+      }
+      if (valid) {
+        const uint32_t idx = (uint32_t)z * plane + pil;
+        if constexpr (FIRST) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t fo = base + q * (int64_t)F1;
+            const T yb = a.ybar[fo + idx];
+            a.P[fo + idx] = ch * yb + h2 * (cq * at[q]);
+            a.Q[fo + idx] = ch * yb;
+          }
+          if constexpr (GRAD)
+            a.grad[idx] += 2.0 * a.h * ((double)cq * (double)a.ybar[base + idx]) * (double)dv;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t fo = base + q * (int64_t)F1;
+            const T qn = a.Q[fo + idx] + h2 * at[q];
+            if (!a.last) {
+              a.Q[fo + idx] = qn;
+            } else {
+              const double l1 = (double)qn;
+              const double v0 = l1 + (double)a.P[fo + idx];
+              const double f0 = a.h * l1;
+              if (a.first_seq) {
+                a.yacc[fo + idx] = v0;
+                a.facc[fo + idx] = f0;
+              } else {
+                a.yacc[fo + idx] += v0;
+                a.facc[fo + idx] += f0;
+              }
+            }
+          }
+          if constexpr (GRAD) a.grad[idx] += 2.0 * a.h * (double)a.P[base + idx] * (double)dv;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 2 * R; ++k) {
+        qa[k] = qa[k + 1];
+        qb[k] = qb[k + 1];
+        if constexpr (GRAD) ql[k] = ql[k + 1];
+      }
+      qa[2 * R] = anext;
+      qb[2 * R] = bnext;
+      if constexpr (GRAD) ql[2 * R] = lnext;
+    }
+  }
+}
+
 template <typename T>
 struct AdjFinalArgs {
   Geometry g;

@@ -2273,6 +2273,16 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
                                       v == GBS_VARIANT_TILE3D);
   const unsigned mblocks = (unsigned)(((P->prob.n[0] + 63) / 64) * ((P->prob.n[1] + 3) / 4) *
                                       ((P->prob.n[2] + 63) / 64));
+  // the LDS-tiled adjoint sweeps with the LDS-tiled forward form, in FP64
+  // (in FP32 the z-marching sweeps at 3 waves per SIMD measured faster than
+  // the tiled ones, whose 512-thread blocks then fit once per CU: 0.66
+  // against 0.70 s per 4 adjoint macro steps at 384^3; FP64 1.18 against
+  // 0.93 s)
+  const bool tiled = OP == OP_AC3D && v == GBS_VARIANT_TILE3D && sizeof(T) == 8;
+  constexpr int ATZ = 128, ABY = 8, AWPE = 2;
+  const unsigned tblocks = (unsigned)(((P->prob.n[0] + 63) / 64) *
+                                      ((P->prob.n[1] + ABY - 1) / ABY) *
+                                      ((P->prob.n[2] + ATZ - 1) / ATZ));
 
   if (tbar && P->nrec)
     hipLaunchKernelGGL(inject_kernel<T>, dim3((unsigned)((P->nrec + 255) / 256)), dim3(256), 0, s,
@@ -2298,6 +2308,29 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
   aa.facc = facc;
   aa.grad = grad;
   aa.nrhs = P->prob.n_rhs;
+  auto adj_sweep = [&](bool first) {
+    if constexpr (OP == OP_AC3D && sizeof(T) == 8) {
+      if (tiled) {
+        const dim3 g(tblocks), b(64 * ABY);
+        if (first) {
+          if (grad) hipLaunchKernelGGL((adj_tile3d<T, ORDER, ATZ, ABY, true, true, AWPE>), g, b, 0, s, aa);
+          else hipLaunchKernelGGL((adj_tile3d<T, ORDER, ATZ, ABY, true, false, AWPE>), g, b, 0, s, aa);
+        } else {
+          if (grad) hipLaunchKernelGGL((adj_tile3d<T, ORDER, ATZ, ABY, false, true, AWPE>), g, b, 0, s, aa);
+          else hipLaunchKernelGGL((adj_tile3d<T, ORDER, ATZ, ABY, false, false, AWPE>), g, b, 0, s, aa);
+        }
+        return;
+      }
+    }
+    if (march) {
+      if (first) hipLaunchKernelGGL((adj_march3d<T, ORDER, 64, true>), dim3(mblocks), dim3(256), 0, s, aa);
+      else hipLaunchKernelGGL((adj_march3d<T, ORDER, 64, false>), dim3(mblocks), dim3(256), 0, s, aa);
+    } else if (first) {
+      hipLaunchKernelGGL((adj_first_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
+    } else {
+      hipLaunchKernelGGL((adj_lf_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
+    }
+  };
 
   for (int r = 0; r < P->k; ++r) {
     const int j = P->order[r];
@@ -2329,20 +2362,14 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
     aa.P = bufA;
     aa.Q = bufB;
     aa.last = 0;
-    if (march)
-      hipLaunchKernelGGL((adj_march3d<T, ORDER, 64, true>), dim3(mblocks), dim3(256), 0, s, aa);
-    else
-      hipLaunchKernelGGL((adj_first_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
+    adj_sweep(true);
     for (int n = N - 1; n >= 1; --n) {
       const bool a_is_p = ((N - 1 - n) % 2) == 0;
       aa.P = a_is_p ? bufA : bufB;
       aa.Q = a_is_p ? bufB : bufA;
       aa.level = n == 0 ? y0 : L[n];
       aa.last = n == 1;
-      if (march)
-        hipLaunchKernelGGL((adj_march3d<T, ORDER, 64, false>), dim3(mblocks), dim3(256), 0, s, aa);
-      else
-        hipLaunchKernelGGL((adj_lf_kernel<T, ORDER, OP>), dim3(gx), dim3(256), 0, s, aa);
+      adj_sweep(false);
     }
   }
   AdjFinalArgs<T> fz;
