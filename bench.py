@@ -132,12 +132,12 @@ def summarize_counters(args):
 
 
 def kernel_names(variant, B):
-    step = {B.VARIANT_TEMPORAL: "gbs::pass2d<double, 4, 7, false, 1, false, false>",
-            B.VARIANT_TEMPORAL4: "gbs::pass2d<double, 4, 4, false, 1, false, false>",
-            B.VARIANT_TEMPORAL_S5: "gbs::pass2d<double, 4, 5, true, 1, false, false>",
-            B.VARIANT_TEMPORAL_S6: "gbs::pass2d<double, 4, 6, true, 1, false, false>",
-            B.VARIANT_TEMPORAL_WG4: "gbs::pass2d<double, 4, 7, false, 4, false, false>",
-            B.VARIANT_TEMPORAL_WG8: "gbs::pass2d<double, 4, 7, false, 8, false, false>",
+    step = {B.VARIANT_TEMPORAL: "gbs::pass2d<double, 4, 7, false, 1, false, false, false>",
+            B.VARIANT_TEMPORAL4: "gbs::pass2d<double, 4, 4, false, 1, false, false, false>",
+            B.VARIANT_TEMPORAL_S5: "gbs::pass2d<double, 4, 5, true, 1, false, false, false>",
+            B.VARIANT_TEMPORAL_S6: "gbs::pass2d<double, 4, 6, true, 1, false, false, false>",
+            B.VARIANT_TEMPORAL_WG4: "gbs::pass2d<double, 4, 7, false, 4, false, false, false>",
+            B.VARIANT_TEMPORAL_WG8: "gbs::pass2d<double, 4, 7, false, 8, false, false, false>",
             B.VARIANT_FLAT: "gbs::lf_kernel<double, 4, 2>"}.get(variant,
                                                               "gbs::lf_march2d<double, 4, ...>")
     temporal = variant in (B.VARIANT_TEMPORAL, B.VARIANT_TEMPORAL4, B.VARIANT_TEMPORAL_S5,
