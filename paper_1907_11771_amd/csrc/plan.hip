@@ -2273,13 +2273,12 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
                                       v == GBS_VARIANT_TILE3D);
   const unsigned mblocks = (unsigned)(((P->prob.n[0] + 63) / 64) * ((P->prob.n[1] + 3) / 4) *
                                       ((P->prob.n[2] + 63) / 64));
-  // the LDS-tiled adjoint sweeps with the LDS-tiled forward form, in FP64
-  // (in FP32 the z-marching sweeps at 3 waves per SIMD measured faster than
-  // the tiled ones, whose 512-thread blocks then fit once per CU: 0.66
-  // against 0.70 s per 4 adjoint macro steps at 384^3; FP64 1.18 against
-  // 0.93 s)
-  const bool tiled = OP == OP_AC3D && v == GBS_VARIANT_TILE3D && sizeof(T) == 8;
-  constexpr int ATZ = 128, ABY = 8, AWPE = 2;
+  // the LDS-tiled adjoint sweeps with the LDS-tiled forward form: 64 x 8
+  // columns per block in FP64 (2 waves per SIMD), 64 x 12 in FP32 (3 waves:
+  // one 768-thread block fills a CU; 64 x 8 blocks fit once per CU and
+  // were slower than the z-marching sweeps)
+  const bool tiled = OP == OP_AC3D && v == GBS_VARIANT_TILE3D;
+  constexpr int ATZ = 128, ABY = sizeof(T) == 4 ? 12 : 8, AWPE = sizeof(T) == 4 ? 3 : 2;
   const unsigned tblocks = (unsigned)(((P->prob.n[0] + 63) / 64) *
                                       ((P->prob.n[1] + ABY - 1) / ABY) *
                                       ((P->prob.n[2] + ATZ - 1) / ATZ));
@@ -2309,7 +2308,7 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
   aa.grad = grad;
   aa.nrhs = P->prob.n_rhs;
   auto adj_sweep = [&](bool first) {
-    if constexpr (OP == OP_AC3D && sizeof(T) == 8) {
+    if constexpr (OP == OP_AC3D) {
       if (tiled) {
         const dim3 g(tblocks), b(64 * ABY);
         if (first) {
