@@ -334,7 +334,8 @@ __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
 // needs registers that make the sweep spill.)
 template <typename T, int ORDER, int TZ, typename Point>
 __device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geometry& g,
-                                             T invx, T invy, T invz, Point point) {
+                                             T invx, T invy, T invz, const int tile,
+                                             Point point) {
   constexpr int R = Fd<ORDER>::R;
   constexpr int BX = 64, BY = 16, LX = BX + 2 * R, LY = BY + 2 * R;
   constexpr int NYH = 2 * R * BX * 2;          // y-halo values (p, v_y) per plane
@@ -345,7 +346,6 @@ __device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geo
   __shared__ T svy[2][LY][BX];
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int ntx = (nx + BX - 1) / BX, nty = (ny + BY - 1) / BY;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
   const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
   const int x0 = tx * BX, y0 = ty * BY, z0 = tz * TZ;
@@ -459,15 +459,39 @@ __device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geo
 template <typename T>
 constexpr int tile3d_waves() { return sizeof(T) == 4 ? 8 : 4; }
 
+// Tiles of the 64 x 16 x TZ blocking of lf_tile3d / first_tile3d.
+template <int TZ>
+__device__ __forceinline__ int tile3d_count(const Geometry& g) {
+  return ((g.nx + 63) / 64) * ((g.ny + 15) / 16) * ((g.nz + TZ - 1) / TZ);
+}
+
+// Workgroup index -> (tile, sequence) for a launch of n sequences over
+// `tiles` tiles: the n workgroups of one tile are consecutive on one XCD
+// (they read the same c^2 tile, which then comes from that XCD's L2), and
+// each XCD works on one contiguous band of tiles as in xcd_tile.
+__device__ __forceinline__ void xcd_tile_seq(int b, int tiles, int n, int& tile, int& seq) {
+  if (tiles % 8) {
+    tile = b / n;
+    seq = b % n;
+    return;
+  }
+  const int i = b / 8;
+  tile = (b % 8) * (tiles / 8) + i / n;
+  seq = i % n;
+}
+
 template <typename T, int ORDER, int TZ>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(tile3d_waves<T>())))
 void lf_tile3d(const StepArgs<T> a) {
-  const SeqDesc<T>& d = a.seq[blockIdx.y];
+  const int tiles = tile3d_count<TZ>(a.g);
+  int tile, sq;
+  xcd_tile_seq(blockIdx.x, tiles, gridDim.x / tiles, tile, sq);
+  const SeqDesc<T>& d = a.seq[sq];
   const int64_t rhs = blockIdx.z;
   const int64_t base = rhs * a.g.state;
   const int64_t F1 = a.g.field;
   tile3d_march<T, ORDER, TZ>(
-      d.cur + base, a.g, a.invx, a.invy, a.invz,
+      d.cur + base, a.g, a.invx, a.invy, a.invz, tile,
       [&](int64_t idx, T dvx, T dvy, T dvz, T* f, const T* c) {
         const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
         f[0] = -(c2 * ((dvx + dvy) + dvz));
@@ -500,7 +524,7 @@ void first_tile3d(const FirstArgs<T> a) {
   const int64_t base = rhs * a.g.state;
   const int64_t F1 = a.g.field;
   tile3d_march<T, ORDER, TZ>(
-      a.y0 + base, a.g, a.invx, a.invy, a.invz,
+      a.y0 + base, a.g, a.invx, a.invy, a.invz, xcd_tile(blockIdx.x, gridDim.x),
       [&](int64_t idx, T dvx, T dvy, T dvz, T* f, const T* c) {
         const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
         f[0] = -(c2 * ((dvx + dvy) + dvz));

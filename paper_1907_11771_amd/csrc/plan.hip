@@ -757,7 +757,7 @@ template <typename T, int ORDER, int OP>
 void launch_lf(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gx, unsigned gz) {
   if constexpr (OP == OP_AC3D && ORDER != GBS_FD_SPECTRAL) {
     if (resolve_variant(P) == GBS_VARIANT_TILE3D) {
-      hipLaunchKernelGGL((lf_tile3d<T, ORDER, TILE_TZ>), dim3(tile3d_blocks(P), n, gz),
+      hipLaunchKernelGGL((lf_tile3d<T, ORDER, TILE_TZ>), dim3(tile3d_blocks(P) * n, 1, gz),
                          dim3(1024), 0, P->stream, sa);
       return;
     }
