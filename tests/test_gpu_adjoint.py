@@ -165,21 +165,25 @@ def test_full_size_gradient_vs_central_differences():
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-14), (torch.float32, 1e-6)])
-def test_adjoint_3d_march_matches_flat(dtype, tol):
+@pytest.mark.parametrize("shape", [(70, 22, 90), (130, 64, 128)])
+def test_adjoint_3d_march_matches_flat(dtype, tol, shape):
     # the z-marching adjoint sweeps against the flat ones: same products and
     # sums (the gradient adds the right-hand sides one at a time), ragged
-    # against the 64 x 4 x 64 tiles
-    shape = (70, 22, 90)
+    # against the 64 x 4 x 64 tiles; the second grid has a multiple of 8
+    # tiles in every tiled form (the XCD-grouped tile orders) and a ragged
+    # last z chunk
+    nz, ny, nx = shape
     cs = fields.lognormal_speed(shape, seed=14)
-    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / 90, 3, workloads.SIGMA_FD8)
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(shape), 3,
+                           workloads.SIGMA_FD8)
     rng = np.random.default_rng(15)
     y0 = to_dev(rng.standard_normal((2, 4) + shape), dtype)
     wbar = rng.standard_normal((2, 4) + shape)
     res = []
     for v in (B.VARIANT_FLAT, B.VARIANT_MARCH8, B.VARIANT_TILE3D):
-        plan = lib_plan(B.ACOUSTIC3D, (90, 22, 70), schemes.ORDER8_K6, H, fd_order=8, n_rhs=2,
+        plan = lib_plan(B.ACOUSTIC3D, (nx, ny, nz), schemes.ORDER8_K6, H, fd_order=8, n_rhs=2,
                         dtype=dtype, c2_field=to_dev(cs ** 2, dtype), c_max=float(cs.max()))
-        plan.set_sources([0], [(30 * 22 + 5) * 90 + 7], [1e3], 25.0, 0.004)
+        plan.set_sources([0], [(30 * ny + 5) * nx + 7], [1e3], 25.0, 0.004)
         plan.set_variant(v)
         ybar = to_dev(wbar, dtype)
         grad = torch.zeros(shape, dtype=torch.float64, device="cuda")

@@ -377,12 +377,13 @@ def test_wave_orders_do_not_change_the_result(order):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("shape", [(70, 22, 90), (64, 32, 128), (9, 9, 9)])
+@pytest.mark.parametrize("shape", [(70, 22, 90), (64, 32, 128), (9, 9, 9), (130, 64, 128)])
 def test_tile3d_matches_flat_and_oracle(dtype, shape):
     # the LDS-tiled 3-D sweeps against the one-point-per-thread ones (the same
     # stencil sums; products may contract differently) and, for the ragged
-    # grid, against the oracle; ragged tiles in x, y and z, and the smallest
-    # grid FD8 allows, smaller than one tile
+    # grid, against the oracle; ragged tiles in x, y and z, the smallest grid
+    # FD8 allows, smaller than one tile, and a grid of 16 tiles (a multiple
+    # of 8: the XCD-grouped orders of tiles and of each tile's sequences)
     nz, ny, nx = shape
     cs = fields.lognormal_speed(shape, seed=27)
     H = workloads.stable_H(workloads.ISB_ORDER8_K6, cs.max(), 1.0 / max(shape), 3,
