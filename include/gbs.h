@@ -287,12 +287,20 @@ int gbs_plan_set_wave_order(gbs_plan* plan, int32_t order);
  *                           in the last launch (and the plan runs on one
  *                           lane), that pass also forms y_out = sum_j c_j y*_j
  *                           instead of a separate combination kernel
+ *   GBS_FORM_ALIGNED_FIRST  the first passes (one launch, every sequence
+ *                           reading y_0) share one strip geometry, that of
+ *                           the widest halo among them, and the workgroups
+ *                           of the sequences for one group of strips are
+ *                           adjacent on one XCD (wave order 2 unless another
+ *                           is set), so that y_0 is read from HBM about once
+ *                           rather than once per sequence; the sequences
+ *                           with fewer evaluations recompute a wider halo
  * Default: 0 (neither: on the 2-D workload both measured slower, the shared
  * F_0 doubling the first passes' reads and the fused tail running one
  * sequence's wavefronts alone).  Errors: GBS_EINVAL (null plan, unknown
  * flags).
  */
-enum { GBS_FORM_SHARED_F0 = 1, GBS_FORM_FUSED_COMBINE = 2 };
+enum { GBS_FORM_SHARED_F0 = 1, GBS_FORM_FUSED_COMBINE = 2, GBS_FORM_ALIGNED_FIRST = 4 };
 int gbs_plan_set_form(gbs_plan* plan, int32_t form);
 int gbs_plan_get_variant(const gbs_plan* plan, int32_t* variant);
 

@@ -23,7 +23,7 @@ VARIANT_TEMPORAL, VARIANT_TEMPORAL4, VARIANT_TEMPORAL_S5, VARIANT_TEMPORAL_S6 = 
 VARIANT_PLAIN = 10
 VARIANT_TEMPORAL_WG4, VARIANT_TEMPORAL_WG8 = 11, 12
 VARIANT_TILE3D = 13
-FORM_SHARED_F0, FORM_FUSED_COMBINE = 1, 2
+FORM_SHARED_F0, FORM_FUSED_COMBINE, FORM_ALIGNED_FIRST = 1, 2, 4
 MAX_SEQ = 16
 MAX_SRC = 16
 MAX_REC = 1024

@@ -595,6 +595,7 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         const int q = rr - sch.round0[j];
         if (lane_of[r] != l || q < 0 || q >= npass[j]) continue;
         PassSeq<T>& d = pa.seq[n++];
+        d.hs = 0;
         const double h = P->H / P->steps[j];
         // the pass's input level is y_{s0}: s0 = evaluations so far (the
         // shared form's first pass starts from the pair (y_0, y_1))
@@ -623,6 +624,22 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
         maxs = std::max(maxs, d.strips);
       }
       if (n == 0) continue;
+      // GBS_FORM_ALIGNED_FIRST: the first passes (all reading y_0) take the
+      // strip geometry of the widest halo among them, so that workgroup u of
+      // every sequence covers the same columns, and run in the grouped
+      // order below, so that those workgroups meet on one XCD and read the
+      // y_0 rows once from HBM
+      const bool aligned = WPG == 1 && n > 1 && (P->form & GBS_FORM_ALIGNED_FIRST) && rr == 0;
+      if (aligned) {
+        int gmax = 0;
+        for (int i = 0; i < n; ++i) gmax = std::max(gmax, pa.seq[i].g);
+        const int wv = 64 - 2 * gmax * R;
+        maxs = (nx + wv - 1) / wv;
+        for (int i = 0; i < n; ++i) {
+          pa.seq[i].hs = gmax * R;
+          pa.seq[i].strips = maxs;
+        }
+      }
       pa.max_strips = maxs;
       {
         int strips = 0, gmax = 0;
@@ -644,7 +661,7 @@ int run_temporal(gbs_plan* P, double t0, int n_macro, const T* yin, T* yout) {
       const unsigned blocks = WPG > 1 ? waves : (waves + 3) / 4;
       dim3 grid(blocks, n, P->prob.n_rhs);
       const dim3 blk(WPG > 1 ? 64 * WPG : 256);
-      pa.order = WPG == 1 && n > 1 ? P->wave_order : 0;
+      pa.order = WPG == 1 && n > 1 ? (aligned && !P->wave_order ? 2 : P->wave_order) : 0;
       if (pa.order) {
         // sequences of one group of 4 units adjacent on one XCD
         pa.nseq = n;
@@ -1125,7 +1142,7 @@ extern "C" int gbs_plan_set_band(gbs_plan* P, int32_t rows) {
 
 extern "C" int gbs_plan_set_form(gbs_plan* P, int32_t form) {
   if (!P) return fail(GBS_EINVAL, "plan is null");
-  if (form & ~(GBS_FORM_SHARED_F0 | GBS_FORM_FUSED_COMBINE))
+  if (form & ~(GBS_FORM_SHARED_F0 | GBS_FORM_FUSED_COMBINE | GBS_FORM_ALIGNED_FIRST))
     return fail(GBS_EINVAL, "unknown form flags 0x%x", form);
   P->form = form;
   return GBS_OK;

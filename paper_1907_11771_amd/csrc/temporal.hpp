@@ -51,7 +51,7 @@ struct PassSeq {
   int32_t g;          // evaluations in this pass (1..G)
   int32_t flags;
   int32_t strips;     // strips along x for this g
-  int32_t pad;
+  int32_t hs;         // recomputed columns on each side of a strip, >= g R (0: g R)
   double amp[PASS_GMAX];  // source wavelet at each evaluation's time
 };
 
@@ -143,6 +143,7 @@ struct PassWork {
   int64_t rhs;         // right-hand-side index (for sources)
   T h, c2c, invx, invy;
   int32_t nx, ny, g, flags, band, nsrc;
+  int32_t hs;          // strip halo in columns, >= g R (0: g R)
   double amp[PASS_GMAX];
 };
 
@@ -202,13 +203,17 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
   const int wave = WPG > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
   const int nx = w.nx, ny = w.ny;
   const int g = w.g;
-  const int halo = g * R;
-  const int wv = 64 * WPG - 2 * halo;
+  const int halo = g * R;                            // rows the levels trail (y)
+  // recomputed columns on each side of the strip: g R, or more where the
+  // passes of one launch share one strip geometry (A_g is exact on lanes
+  // [g R, 64 - g R), so any wider halo stores exact values)
+  const int hxs = w.hs > halo ? w.hs : halo;
+  const int wv = 64 * WPG - 2 * hxs;
   const int x0 = strip * wv;
-  const int col = x0 - halo + 64 * wave + lane;      // unwrapped column of this lane
+  const int col = x0 - hxs + 64 * wave + lane;       // unwrapped column of this lane
   const int gx = pmod(col, nx);
   const int gl = 64 * wave + lane;                   // lane within the workgroup
-  const bool lane_ok = gl >= halo && gl < 64 * WPG - halo && col < nx;
+  const bool lane_ok = gl >= hxs && gl < 64 * WPG - hxs && col < nx;
   const bool has_left = WPG > 1 && wave > 0, has_right = WPG > 1 && wave < WPG - 1;
   const bool edge_lane = lane < R || lane >= 64 - R;
   const int edge_idx = lane < R ? lane : R + lane - (64 - R);
@@ -479,6 +484,7 @@ void pass2d(const PassArgs<T> a) {
   w.flags = d.flags;
   w.band = a.band;
   w.nsrc = a.g.nsrc;
+  w.hs = WPG == 1 ? d.hs : 0;
 #pragma unroll
   for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = d.amp[e];
   pass_body<T, ORDER, G, SKEW1, WPG, VARC, KEEP, COMB>(w, strip, band);
@@ -623,6 +629,7 @@ void pass2d_batch(const BatchPassArgs<T> a) {
   w.flags = it->flags;
   w.band = it->band;
   w.nsrc = 0;
+  w.hs = 0;
 #pragma unroll
   for (int e = 0; e < PASS_GMAX; ++e) w.amp[e] = 0.0;
   if (w.c2f)

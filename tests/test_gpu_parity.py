@@ -347,12 +347,15 @@ def test_plan_follows_torchs_current_stream():
 
 @pytest.mark.parametrize("variant", [B.VARIANT_TEMPORAL_S5, B.VARIANT_TEMPORAL])
 @pytest.mark.parametrize("form", [B.FORM_SHARED_F0, B.FORM_FUSED_COMBINE,
-                                  B.FORM_SHARED_F0 | B.FORM_FUSED_COMBINE])
+                                  B.FORM_SHARED_F0 | B.FORM_FUSED_COMBINE,
+                                  B.FORM_ALIGNED_FIRST,
+                                  B.FORM_ALIGNED_FIRST | B.FORM_SHARED_F0])
 def test_pass_forms_vs_oracle(form, variant):
-    # f(t0, y0) shared by the first passes (Sect. 3.6) and the combination
-    # folded into the last sequence's final pass: the oracle's values (with
-    # the five sources of the multi-source problem, c^2 field, two
-    # right-hand sides) and the default form's to rounding
+    # f(t0, y0) shared by the first passes (Sect. 3.6), the combination
+    # folded into the last sequence's final pass, and the first passes on one
+    # strip geometry: the oracle's values (with the five sources of the
+    # multi-source problem, c^2 field, two right-hand sides) and the default
+    # form's to rounding
     plan, ops, H, t0 = multi_source_problem()
     steps, c = oracle_weights(schemes.ORDER8_K6)
     plan.set_variant(variant)
@@ -364,6 +367,25 @@ def test_pass_forms_vs_oracle(form, variant):
         want = G.integrate(ops[r], t0, y0[r], H, 3, steps, c)
         assert rel_err(got[r], want, 0) <= TOL64, r
     assert rel_err(got, ref, 1) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("variant,order", [(B.VARIANT_TEMPORAL_S5, 0), (B.VARIANT_TEMPORAL4, 0),
+                                           (B.VARIANT_TEMPORAL, 0), (B.VARIANT_TEMPORAL_S5, 1)])
+def test_aligned_first_passes_equal_the_default(dtype, variant, order):
+    # every column's value comes from the same arithmetic whichever strip
+    # and lane compute it, so the first passes on the widest halo's strip
+    # geometry (wider recomputed halo for the passes with fewer evaluations,
+    # 3 strips of 44 columns for 100, sources in several columns) change no
+    # bit; with the hardware order or another workgroup order as well
+    plan, ops, H, t0 = multi_source_problem(dtype)
+    plan.set_variant(variant)
+    y0 = to_dev(1e-3 * np.random.default_rng(29).standard_normal((2, 3) + ops[0].shape), dtype)
+    ref = plan.step(y0, t0=t0, n_macro=2)
+    plan.set_form(B.FORM_ALIGNED_FIRST)
+    plan.set_wave_order(order)
+    got = plan.step(y0, t0=t0, n_macro=2)
+    assert torch.equal(got, ref)
 
 
 @pytest.mark.parametrize("order", [1, 2])

@@ -1,9 +1,10 @@
 """The paper's published schemes through the same kernels: the fully
 determined optimum schemes of order 8, 12 and 16 (Sect. 3.3, Table 1) and
 the methods of choice GBS_{8,6}, GBS_{8,8} and GBS_{12,8} (Sect. 3.8; up to
-15 sequences, N_max = 30), each on a 2-D acoustic problem with a c^2 field
-and a source at 0.8 of the scheme's own stability limit, in the blocked and
-the streaming forms, against the oracle."""
+15 sequences, N_max = 30), and the smallest scheme, order 4 over N = {2, 4}
+(two sequences, one blocked launch), each on a 2-D acoustic problem with a
+c^2 field and a source at 0.8 of the scheme's own stability limit, in the
+blocked and the streaming forms, against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -18,7 +19,7 @@ from tests.gpu_util import lib_plan, oracle_weights, rel_err, to_dev
 pytestmark = pytest.mark.gpu
 
 PUBLISHED = [schemes.FULLDET8, schemes.FULLDET12, schemes.FULLDET16, schemes.GBS_8_6,
-             schemes.GBS_8_8, schemes.GBS_12_8]
+             schemes.GBS_8_8, schemes.GBS_12_8, schemes.SQUARE4_2_4]
 
 
 @pytest.mark.parametrize("sch", PUBLISHED, ids=[s["name"] for s in PUBLISHED])
