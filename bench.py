@@ -3,13 +3,17 @@
 MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint]
+                    [--no-batch] [--no-3d]
 
 One "step" is one macro step: all six GBS sequences (forward Euler, N_j
 leap-frog steps, averaging) and the FP64 weighted combination, i.e.
 1 + sum N_j = 43 RHS evaluations per grid point.  Prints one JSON line; its
 "fwd_adj" object is the metric's second half, forward + adjoint time at
 fixed error against the plain form (the 1024^2 differentiation workload,
-400 macro steps), with the adjoint pass kernel's roofline.
+400 macro steps), with the adjoint pass kernel's roofline; "batch64" holds
+the batch workload in FP64 and FP32 stepping (100 macro steps) and
+"acoustic3d" the 384^3 FD8 forward with 8 right-hand sides (FP32 stepping,
+FP64 and the plain FP64 form beside it, LEG_3D_MACRO_STEPS macro steps).
 """
 import argparse
 import json
@@ -22,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 STREAM_BYTES_PER_UPDATE = 72.0   # FP64 2-D acoustic leap-frog update, streaming: 3 F b
+LEG_3D_MACRO_STEPS = 10    # macro steps of the default line's 3-D forward leg
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1907_11771_amd", "csrc")
 
@@ -221,28 +226,33 @@ def cpu_folded(cfg, updates):
                        % ([[n for n, _ in g] for g in groups], dt))
 
 
-def bench_batch(args):
+def batch_inputs():
+    """The 64 instances (size, speed field, H) and their initial states:
+    smooth ones (the 2-D workload's construction: a Gaussian pulse plus 32
+    plane waves up to wavenumber 16, seed per instance), so that the FP32
+    error is stated on representative data."""
+    from synth import fields, workloads
+    inst = workloads.batch_instances(workloads.CONFIG_BATCH)
+    y0 = [fields.acoustic2d_pulse_modes(n, seed=100 + i)[None] for i, (n, _, _) in enumerate(inst)]
+    return inst, y0
+
+
+def batch_leg(n_macro, warmup, dtype_name, plain=True, inputs=None):
     """64 uneven instances advanced in one batch (graph-replayed macro steps,
-    autotuned variant and band), against the plain FP64 form (one streaming
-    launch per sequence per leap-frog step, instance by instance)."""
-    import numpy as np
+    autotuned variant and band) for ``n_macro`` timed macro steps, in FP64 or
+    FP32 stepping (then with the error against the FP64 batch after the same
+    steps), and the plain FP64 form (one streaming launch per sequence per
+    leap-frog step, instance by instance) per macro step."""
     import torch
     from paper_1907_11771_amd import binding as B
     from paper_1907_11771_amd.plan import GBSBatch, GBSPlan, scheme_weights
     from synth import workloads
 
     cfg = workloads.CONFIG_BATCH
-    if args.steps == 500:                 # the default: the batch workload's own length
-        args.steps = cfg["n_macro"]
     steps, w, _ = scheme_weights(cfg["scheme"])
     dev = torch.device("cuda:0")
-    dtype = torch.float64 if args.dtype == "f64" else torch.float32
-    inst = workloads.batch_instances(cfg)
-    # smooth initial states (the 2-D workload's construction: a Gaussian
-    # pulse plus 32 plane waves up to wavenumber 16, seed per instance), so
-    # that the FP32 error is stated on representative data
-    from synth import fields
-    y0 = [fields.acoustic2d_pulse_modes(n, seed=100 + i)[None] for i, (n, _, _) in enumerate(inst)]
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    inst, y0 = inputs or batch_inputs()
     spec = [dict(n=(n, n), H=H, c2_field=torch.from_numpy(c * c).to(dev), c_max=float(c.max()))
             for n, c, H in inst]
     batch = GBSBatch(spec, 8, steps, w, dtype=dtype, device=dev)
@@ -251,14 +261,15 @@ def bench_batch(args):
     del tune
     batch.set_graph(True)
     ys = [torch.from_numpy(a).to(dev, dtype) for a in y0]
-    batch.step(ys, n_macro=max(args.warmup, 1))
+    batch.step(ys, n_macro=max(warmup, 1))
     ys = [torch.from_numpy(a).to(dev, dtype) for a in y0]
     torch.cuda.synchronize()
     t = time.perf_counter()
-    batch.step(ys, n_macro=args.steps)
+    batch.step(ys, n_macro=n_macro)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    upd = batch.updates_per_macro_step() * args.steps
+    upd = batch.updates_per_macro_step() * n_macro
+    del batch
 
     # accuracy of this run against the FP64 batch after the same steps
     err = None
@@ -266,38 +277,58 @@ def bench_batch(args):
         ref = GBSBatch(spec, 8, steps, w, dtype=torch.float64, device=dev)
         ref.set_variant(variant, band)
         yr = [torch.from_numpy(a).to(dev) for a in y0]
-        ref.step(yr, n_macro=args.steps)
+        ref.step(yr, n_macro=n_macro)
         err = max(float((a.double() - b).abs().max() / b.abs().max()) for a, b in zip(ys, yr))
         del ref, yr
 
     # the plain FP64 form on the same instances (a few macro steps, per macro step)
-    plain_steps = 3
-    plain_s = 0.0
-    for (n, c, H), a in zip(inst, y0):
-        pl = GBSPlan(B.ACOUSTIC2D, (n, n), 8, steps, w, H, dtype=torch.float64,
-                     c2_field=torch.from_numpy(c * c).to(dev), c_max=float(c.max()), device=dev)
-        pl.set_variant(B.VARIANT_PLAIN)
-        y = torch.from_numpy(a).to(dev)
-        pl.step(y, y, n_macro=1)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        pl.step(y, y, n_macro=plain_steps)
-        torch.cuda.synchronize()
-        plain_s += time.perf_counter() - t
-        del pl, y
-    plain_ms = plain_s * 1e3 / plain_steps
-    rec = dict(
-        metric="grid-pt RHS updates/s", value=upd / dt, unit="grid-pt RHS updates/s",
-        n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=dt * 1e3 / args.steps,
-        higher_is_better=True, scaling="weak", vs_baseline=None, dtype=args.dtype,
-        data="synthetic",
+    plain_ms = None
+    if plain:
+        plain_steps = 3
+        plain_s = 0.0
+        for (n, c, H), a in zip(inst, y0):
+            pl = GBSPlan(B.ACOUSTIC2D, (n, n), 8, steps, w, H, dtype=torch.float64,
+                         c2_field=torch.from_numpy(c * c).to(dev), c_max=float(c.max()),
+                         device=dev)
+            pl.set_variant(B.VARIANT_PLAIN)
+            y = torch.from_numpy(a).to(dev)
+            pl.step(y, y, n_macro=1)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pl.step(y, y, n_macro=plain_steps)
+            torch.cuda.synchronize()
+            plain_s += time.perf_counter() - t
+            del pl, y
+        plain_ms = plain_s * 1e3 / plain_steps
+    del spec, ys
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    ms = dt * 1e3 / n_macro
+    return dict(
+        updates_per_s=upd / dt, ms_per_step=ms, steps=n_macro, dtype=dtype_name,
         config=dict(workload=cfg["name"], instances=len(inst),
                     sizes=sorted(set(n for n, _, _ in inst)), points=sum(n * n for n, _, _ in inst),
                     evals_per_macro_step=1 + sum(steps), graph=True,
                     autotuned=dict(variant=variant, band=band)),
         plain_fp64_ms_per_step=plain_ms,
-        speedup_vs_plain_fp64=plain_ms / (dt * 1e3 / args.steps),
-        max_rel_err_vs_fp64=err,
+        speedup_vs_plain_fp64=plain_ms / ms if plain_ms else None,
+        max_rel_err_vs_fp64=err)
+
+
+def bench_batch(args):
+    """The batch workload on its own line (batch_leg)."""
+    from synth import workloads
+    if args.steps == 500:                 # the default: the batch workload's own length
+        args.steps = workloads.CONFIG_BATCH["n_macro"]
+    leg = batch_leg(args.steps, args.warmup, args.dtype)
+    rec = dict(
+        metric="grid-pt RHS updates/s", value=leg["updates_per_s"], unit="grid-pt RHS updates/s",
+        n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=leg["ms_per_step"],
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype=args.dtype,
+        data="synthetic", config=leg["config"],
+        plain_fp64_ms_per_step=leg["plain_fp64_ms_per_step"],
+        speedup_vs_plain_fp64=leg["speedup_vs_plain_fp64"],
+        max_rel_err_vs_fp64=leg["max_rel_err_vs_fp64"],
     )
     print(json.dumps(rec), flush=True)
 
@@ -434,29 +465,17 @@ def adjoint_leg(n_macro=None, grid=None):
     return rec_out
 
 
-def bench_3d(args):
-    """384^3 FD8 acoustic, 8 right-hand sides (one Ricker point source each).
-    Forward: FP32 stepping with the FP64 combination over all 8 right-hand
-    sides in one plan, and the same steps in FP64 for the error statement.
-    Gradient: receiver misfit against data from a perturbed c^2 (FP64, all
-    8 right-hand sides), forward + checkpointed adjoint in FP32 stepping,
-    run in groups of right-hand sides so that checkpoints, recomputed
-    states and the adjoint's levels fit in HBM; the FP32 gradient of the
-    first group is compared with the FP64 one."""
+def problem_3d():
+    """The 384^3 FD8 workload's inputs: c^2, the perturbed c^2 the misfit's
+    data come from, H at the stability limit of the faster of the two, the
+    8 Ricker point sources and the receivers."""
     import numpy as np
-    import torch
-    from paper_1907_11771_amd import binding as B
-    from paper_1907_11771_amd.autograd import receiver_traces
-    from paper_1907_11771_amd.plan import GBSPlan, scheme_weights
+    from paper_1907_11771_amd.plan import scheme_weights
     from synth import fields, workloads
 
     cfg = workloads.CONFIG_3D
     n, R = cfg["n"], cfg["n_rhs"]
-    nm = cfg["n_macro"] if args.steps == 500 else args.steps
-    ck = cfg["checkpoint_every"]
     steps, w, _ = scheme_weights(cfg["scheme"])
-    dev = torch.device("cuda:0")
-    log = lambda *a: print(*a, file=sys.stderr, flush=True)
     cs = fields.bandlimited_lognormal_speed(n, seed=cfg["speed_seed"], kmax=cfg["kmax"])
     c2 = cs * cs
     g_obs = np.log(fields.bandlimited_lognormal_speed(n, seed=cfg["data_seed"],
@@ -467,30 +486,48 @@ def bench_3d(args):
     H = workloads.stable_H(workloads.ISB_ORDER8_K6, c_top, 1.0 / n, 3, workloads.SIGMA_FD8)
     src = fields.ricker_source_3d(n, workloads.sources_3d(n, R, cfg["source_seed"]))
     rec = fields.plane_receivers_3d(n, cfg["receivers"])
-    log("acoustic3d: fields ready, H = %.6g" % H)
+    return dict(cfg=cfg, n=n, R=R, steps=steps, w=w, c2=c2, c2_obs=c2_obs, c_top=c_top, H=H,
+                src=src, rec=rec)
 
-    def make(dtype, rhs, c2_host, receivers=False):
-        pl = GBSPlan(B.ACOUSTIC3D, (n, n, n), 8, steps, w, H, fd_order=8, n_rhs=len(rhs),
-                     dtype=dtype, c2_field=torch.from_numpy(c2_host).to(dev), c_max=c_top,
-                     device=dev)
-        if args.variant:
-            pl.set_variant(args.variant)
-        pts = [src["points"][r] for r in rhs]
-        pl.set_sources(list(range(len(rhs))), [z * n * n + y * n + x for z, y, x in pts],
-                       [src["weight"]] * len(rhs), src["f0"], src["delay"])
-        if receivers:
-            pl.set_receivers([i for i in range(len(rhs)) for _ in rec],
-                             [z * n * n + y * n + x for _ in rhs for z, y, x in rec])
-        return pl
+
+def make_plan_3d(pb, dtype, rhs, c2_host, variant=0, receivers=False):
+    import torch
+    from paper_1907_11771_amd import binding as B
+    from paper_1907_11771_amd.plan import GBSPlan
+    n, src, rec = pb["n"], pb["src"], pb["rec"]
+    pl = GBSPlan(B.ACOUSTIC3D, (n, n, n), 8, pb["steps"], pb["w"], pb["H"], fd_order=8,
+                 n_rhs=len(rhs), dtype=dtype, c2_field=torch.from_numpy(c2_host).to("cuda:0"),
+                 c_max=pb["c_top"], device=torch.device("cuda:0"))
+    if variant:
+        pl.set_variant(variant)
+    pts = [src["points"][r] for r in rhs]
+    pl.set_sources(list(range(len(rhs))), [z * n * n + y * n + x for z, y, x in pts],
+                   [src["weight"]] * len(rhs), src["f0"], src["delay"])
+    if receivers:
+        pl.set_receivers([i for i in range(len(rhs)) for _ in rec],
+                         [z * n * n + y * n + x for _ in rhs for z, y, x in rec])
+    return pl
+
+
+def forward_3d_leg(nm, variant=0, pb=None):
+    """The 384^3 FD8 forward, all 8 right-hand sides in one plan: FP32
+    stepping with the FP64 combination and the same ``nm`` macro steps in
+    FP64 (the FP32 pressure error is stated against it), and the plain FP64
+    form (one streaming launch per sequence per leap-frog step) per macro
+    step."""
+    import torch
+    from paper_1907_11771_amd import binding as B
+    pb = pb or problem_3d()
+    n, R = pb["n"], pb["R"]
+    dev = torch.device("cuda:0")
 
     def release():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
 
-    # forward throughput, all right-hand sides in one plan
     res, finals = {}, {}
     for dtype in (torch.float32, torch.float64):
-        pl = make(dtype, range(R), c2)
+        pl = make_plan_3d(pb, dtype, range(R), pb["c2"], variant)
         y = torch.zeros((R, 4, n, n, n), dtype=dtype, device=dev)
         pl.step(y, y, n_macro=1)
         y.zero_()
@@ -500,13 +537,14 @@ def bench_3d(args):
         torch.cuda.synchronize()
         res[dtype] = time.perf_counter() - t
         finals[dtype] = y[:, 0].cpu().double()
-        log("acoustic3d forward %s: %.3f s for %d macro steps" % (dtype, res[dtype], nm))
+        print("acoustic3d forward %s: %.3f s for %d macro steps" % (dtype, res[dtype], nm),
+              file=sys.stderr, flush=True)
         del pl, y
         release()
-    # the plain FP64 form: one streaming launch per sequence per leap-frog
-    # step (a few macro steps suffice: the cost per macro step is constant)
+    # the plain FP64 form (a few macro steps suffice: the cost per macro step
+    # is constant)
     n_plain = min(nm, 3)
-    pl = make(torch.float64, range(R), c2)
+    pl = make_plan_3d(pb, torch.float64, range(R), pb["c2"])
     pl.set_variant(B.VARIANT_PLAIN)
     y = torch.zeros((R, 4, n, n, n), dtype=torch.float64, device=dev)
     pl.step(y, y, n_macro=1)
@@ -515,24 +553,57 @@ def bench_3d(args):
     pl.step(y, y, n_macro=n_plain)
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t) * 1e3 / n_plain
-    log("acoustic3d plain FP64: %.1f ms per macro step" % plain_ms)
     del pl, y
     release()
-    t32 = res[torch.float32]
-    fwd_err = float((finals[torch.float32] - finals[torch.float64]).abs().max()
-                    / finals[torch.float64].abs().max())
-    del finals
-    upd = n ** 3 * R * (1 + sum(steps)) * nm
-    line = dict(
-        metric="grid-pt RHS updates/s", value=upd / t32, unit="grid-pt RHS updates/s",
-        n_gpus=1, steps=nm, warmup=1, ms_per_step=t32 * 1e3 / nm, higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload=cfg["name"], grid=[n, n, n], n_rhs=R, fd_order=8),
-        fp64_ms_per_step=res[torch.float64] * 1e3 / nm,
-        fp32_max_rel_err_vs_fp64_pressure=fwd_err,
+    t32, t64 = res[torch.float32], res[torch.float64]
+    err = float((finals[torch.float32] - finals[torch.float64]).abs().max()
+                / finals[torch.float64].abs().max())
+    upd = n ** 3 * R * (1 + sum(pb["steps"])) * nm
+    return dict(
+        updates_per_s=upd / t32, ms_per_step=t32 * 1e3 / nm, steps=nm, dtype="f32",
+        config=dict(workload=pb["cfg"]["name"], grid=[n, n, n], n_rhs=R, fd_order=8),
+        fp64_ms_per_step=t64 * 1e3 / nm,
+        fp32_max_rel_err_vs_fp64_pressure=err,
         plain_fp64_ms_per_step=plain_ms,
-        speedup_vs_plain=dict(fp64=plain_ms / (res[torch.float64] * 1e3 / nm),
-                              fp32=plain_ms / (t32 * 1e3 / nm)))
+        speedup_vs_plain=dict(fp64=plain_ms / (t64 * 1e3 / nm), fp32=plain_ms / (t32 * 1e3 / nm)))
+
+
+def bench_3d(args):
+    """384^3 FD8 acoustic, 8 right-hand sides (one Ricker point source each).
+    Forward: forward_3d_leg.  Gradient: receiver misfit against data from a
+    perturbed c^2 (FP64, all 8 right-hand sides), forward + checkpointed
+    adjoint in FP32 stepping, run in groups of right-hand sides so that
+    checkpoints, recomputed states and the adjoint's levels fit in HBM; the
+    FP32 gradient of the first group is compared with the FP64 one."""
+    import numpy as np
+    import torch
+    from paper_1907_11771_amd.autograd import receiver_traces
+
+    pb = problem_3d()
+    cfg, n, R = pb["cfg"], pb["n"], pb["R"]
+    nm = cfg["n_macro"] if args.steps == 500 else args.steps
+    ck = cfg["checkpoint_every"]
+    c2, c2_obs, rec = pb["c2"], pb["c2_obs"], pb["rec"]
+    dev = torch.device("cuda:0")
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    log("acoustic3d: fields ready, H = %.6g" % pb["H"])
+
+    def make(dtype, rhs, c2_host, receivers=False):
+        return make_plan_3d(pb, dtype, rhs, c2_host, args.variant, receivers)
+
+    def release():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+    leg = forward_3d_leg(nm, args.variant, pb)
+    line = dict(
+        metric="grid-pt RHS updates/s", value=leg["updates_per_s"], unit="grid-pt RHS updates/s",
+        n_gpus=1, steps=nm, warmup=1, ms_per_step=leg["ms_per_step"], higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic", config=leg["config"],
+        fp64_ms_per_step=leg["fp64_ms_per_step"],
+        fp32_max_rel_err_vs_fp64_pressure=leg["fp32_max_rel_err_vs_fp64_pressure"],
+        plain_fp64_ms_per_step=leg["plain_fp64_ms_per_step"],
+        speedup_vs_plain=leg["speedup_vs_plain"])
     if args.no_gradient:
         print(json.dumps(line), flush=True)
         return
@@ -754,6 +825,10 @@ def main():
                     help="leave out the lanes-tuned timing of the default line")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="leave out the forward + adjoint leg of the default line")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="leave out the batch workload's leg of the default line")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="leave out the 3-D forward leg of the default line")
     ap.add_argument("--summarize-counters", nargs=4,
                     metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="print the TRAFFIC line of --kernel from rocprofv3 counter files")
@@ -904,6 +979,21 @@ def main():
         # the metric's second half: forward + adjoint time at fixed error
         # against the plain form, with the adjoint pass kernel's roofline
         rec["fwd_adj"] = adjoint_leg()
+    if not args.no_batch:
+        # the batch workload (64 uneven instances, one graph-replayed batch)
+        # in FP64 and FP32 stepping over its 100 macro steps
+        inputs = batch_inputs()
+        nb = workloads.CONFIG_BATCH["n_macro"]
+        b64 = batch_leg(nb, 2, "f64", inputs=inputs)
+        b32 = batch_leg(nb, 2, "f32", plain=False, inputs=inputs)
+        b32["plain_fp64_ms_per_step"] = b64["plain_fp64_ms_per_step"]
+        b32["speedup_vs_plain_fp64"] = b64["plain_fp64_ms_per_step"] / b32["ms_per_step"]
+        rec["batch64"] = dict(f64=b64, f32=b32)
+        del inputs
+    if not args.no_3d:
+        # the 384^3 FD8 forward with 8 right-hand sides (FP32 stepping, FP64
+        # for the error statement, the plain FP64 form)
+        rec["acoustic3d"] = forward_3d_leg(LEG_3D_MACRO_STEPS)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(cfg, y0)
     print(json.dumps(rec), flush=True)

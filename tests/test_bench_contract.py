@@ -43,3 +43,14 @@ def test_headline_json_line():
     ar = fa["roofline"]
     assert ar["kernel"].startswith("gbs::adj_pass2d<double") and ar["launches"] > 0
     assert abs(ar["frac"] - ar["achieved"] / ar["peak"]) < 1e-9
+    # the batch workload in both precisions, faster than the plain FP64 form,
+    # FP32 within its stated error
+    bt = line["batch64"]
+    assert bt["f64"]["speedup_vs_plain_fp64"] > 1.0 and bt["f64"]["steps"] == 100
+    assert bt["f32"]["ms_per_step"] < bt["f64"]["ms_per_step"]
+    assert bt["f32"]["max_rel_err_vs_fp64"] < 1e-4
+    # the 3-D forward with 8 right-hand sides
+    a3 = line["acoustic3d"]
+    assert a3["config"]["grid"] == [384, 384, 384] and a3["config"]["n_rhs"] == 8
+    assert a3["speedup_vs_plain"]["fp64"] > 1.0 and a3["speedup_vs_plain"]["fp32"] > 1.0
+    assert a3["fp32_max_rel_err_vs_fp64_pressure"] < 1e-4
