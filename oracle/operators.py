@@ -66,13 +66,17 @@ class Acoustic:
     """First-order acoustic system in d = 2 or 3 dimensions:
         p_t = -c^2 div v (+ sources),   v_t = -grad p,
     state fields (p, v_x, v_y[, v_z]); ``c2`` is a scalar or a field of the
-    grid's shape.  Stencil order 2r (r = 2: FD4, r = 4: FD8)."""
+    grid's shape.  Stencil order 2r (r = 2: FD4, r = 4: FD8).  ``spacing``:
+    the grid spacing per axis in the order of ``shape`` (default 1/n, the
+    periodic unit box; a window cut from a larger grid keeps that grid's
+    spacing)."""
 
-    def __init__(self, shape, c2=1.0, r=2, sources=()):
+    def __init__(self, shape, c2=1.0, r=2, sources=(), spacing=None):
         self.shape = tuple(shape)                    # (Y, X) or (Z, Y, X)
         self.d = len(self.shape)
         self.r = r
-        self.dx = [1.0 / n for n in self.shape]      # per axis, same order as shape
+        self.dx = ([1.0 / n for n in self.shape] if spacing is None
+                   else [float(h) for h in spacing])  # per axis, same order as shape
         self.c2 = c2
         self.sources = list(sources)
 

@@ -2,7 +2,9 @@
 384^3 field sampled every 4th point, the same 8 source positions): FP64
 against the oracle, FP32 stepping against the oracle with a stated bound,
 the right-hand sides of one batched plan against single-source plans, and
-the adjoint against the oracle's discrete adjoint."""
+the adjoint against the oracle's discrete adjoint; and at its full size
+(384^3, 8 right-hand sides, the benchmark's launch configuration), sampled
+outputs against the oracle on periodic windows around them."""
 import numpy as np
 import pytest
 import torch
@@ -143,3 +145,63 @@ def test_acoustic3d_checkpointed_gradient_vs_oracle(dtype):
     print(dtype, "3-D gradient vs oracle: L", e_l, "dL/dy0", e_y, "dL/dc2", e_g)
     tol = 1e-11 if dtype == torch.float64 else TOL32_GRAD
     assert e_l <= tol and e_y <= tol and e_g <= tol
+
+
+def test_full_size_384_eight_rhs_sampled_windows_vs_oracle():
+    # the 384^3 workload itself, in the launch configuration the benchmark
+    # times (one plan, all 8 right-hand sides with their sources, the
+    # LDS-tiled sweeps, FP32 stepping and FP64), one macro step, sampled: the
+    # oracle runs on periodic windows of half-width 56 around two points,
+    # with the full grid's spacing, and is exact at the 9^3 points within 4
+    # of each window's middle (the longest sequence's 13 evaluations reach
+    # 13 x 4 = 52 points).  The input is random inside the two windows (right-
+    # hand side 0 around its source, right-hand side 5 across the periodic
+    # boundary) and zero elsewhere.
+    cfg = workloads.CONFIG_3D
+    n, R = cfg["n"], cfg["n_rhs"]
+    hw, k = 56, 4
+    steps, c = oracle_weights(schemes.ORDER8_K6)
+    cs = fields.bandlimited_lognormal_speed(n, seed=cfg["speed_seed"], kmax=cfg["kmax"])
+    c2 = cs ** 2
+    cmax = float(cs.max())
+    H = workloads.stable_H(workloads.ISB_ORDER8_K6, cmax, 1.0 / n, 3, workloads.SIGMA_FD8)
+    src = fields.ricker_source_3d(n, workloads.sources_3d(n, R, cfg["source_seed"]))
+    t0 = src["delay"] - 0.5 * H
+    rng = np.random.default_rng(63)
+    centres = {0: tuple(p + d for p, d in zip(src["points"][0], (3, -2, 1))),
+               5: (2, n - 3, n // 2)}
+    blocks = {r: rng.standard_normal((4,) + (2 * hw + 1,) * 3) for r in centres}
+    idx = {r: [np.arange(q - hw, q + hw + 1) % n for q in ctr] for r, ctr in centres.items()}
+    # the oracle on each window (its own source where it lies inside)
+    want = {}
+    for r, (iz, iy, ix) in idx.items():
+        lo = [q - hw for q in centres[r]]
+        local = [tuple((p - l) % n for p, l in zip(src["points"][r], lo))]
+        local = [q for q in local if all(v <= 2 * hw for v in q)]
+        op = OP.Acoustic((2 * hw + 1,) * 3, c2=c2[np.ix_(iz, iy, ix)], r=4,
+                         spacing=(1.0 / n,) * 3,
+                         sources=[OP.Source(q, src["f0"], src["delay"], src["weight"])
+                                  for q in local])
+        full = G.macro_step(op, t0, blocks[r], H, steps, c)
+        want[r] = full[:, hw - k:hw + k + 1, hw - k:hw + k + 1, hw - k:hw + k + 1]
+    for dtype, tol in ((torch.float32, TOL32), (torch.float64, TOL64)):
+        y = torch.zeros((R, 4, n, n, n), dtype=dtype, device="cuda")
+        for r, (iz, iy, ix) in idx.items():
+            tz, ty, tx = [torch.from_numpy(a).cuda() for a in (iz, iy, ix)]
+            y[r][:, tz[:, None, None], ty[None, :, None], tx[None, None, :]] = \
+                torch.from_numpy(blocks[r]).to("cuda", dtype)
+        plan = lib_plan(B.ACOUSTIC3D, (n, n, n), schemes.ORDER8_K6, H, fd_order=8, n_rhs=R,
+                        dtype=dtype, c2_field=to_dev(c2, dtype), c_max=cmax)
+        assert plan.variant() == B.VARIANT_TILE3D
+        plan.set_sources(list(range(R)), [z * n * n + yy * n + x for z, yy, x in src["points"]],
+                         [src["weight"]] * R, src["f0"], src["delay"])
+        plan.step(y, out=y, t0=t0, n_macro=1)
+        for r, (iz, iy, ix) in idx.items():
+            tz, ty, tx = [torch.from_numpy(a[hw - k:hw + k + 1]).cuda() for a in (iz, iy, ix)]
+            got = y[r][:, tz[:, None, None], ty[None, :, None], tx[None, None, :]]
+            e = rel_err(got.double().cpu().numpy(), want[r], 0)
+            print("384^3", dtype, "rhs", r, "vs oracle window", e, flush=True)
+            assert e <= tol, (dtype, r, e)
+        del plan, y
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()

@@ -173,3 +173,37 @@ def test_unstable_step_grows():
     y = np.random.default_rng(0).standard_normal((3, n, n))
     y1 = G.integrate(op, 0.0, y, H, 40, steps, c)
     assert np.sum(y1 ** 2) > 1e3 * np.sum(y ** 2)
+
+
+def test_periodic_window_reproduces_the_full_grid_at_its_centre():
+    # the output of one macro step at a point depends on the input within
+    # (N_max + 1) r points of it (each of the longest sequence's N_max + 1
+    # evaluations reaches r points further), so the oracle run on a
+    # periodic window of half-width W around a point, with the full grid's
+    # spacing, gives the full grid's values at the window's centre points
+    # within W - (N_max + 1) r of the middle: the same arithmetic, bitwise.
+    # (2-D FD8 here; the 3-D full-size parity test samples its outputs so.)
+    n, r, hw = 128, 4, 56
+    steps, c = _cf(schemes.ORDER8_K6)
+    reach = (max(steps) + 1) * r                        # 52
+    cs = fields.lognormal_speed((n, n), seed=90)
+    rng = np.random.default_rng(91)
+    y0 = rng.standard_normal((3, n, n))
+    H = 0.5 / n
+    src_pt = (70, 40)
+    ops = OP.Acoustic((n, n), c2=cs ** 2, r=r, sources=[OP.Source(src_pt, 9.0, 0.1, 50.0)])
+    full = G.macro_step(ops, 0.09, y0, H, steps, c)
+    ctr = (64, 37)
+    iy, ix = [np.arange(q - hw, q + hw + 1) % n for q in ctr]
+    win = np.ix_(iy, ix)
+    local = tuple(p - (q - hw) for p, q in zip(src_pt, ctr))
+    opw = OP.Acoustic((2 * hw + 1,) * 2, c2=(cs ** 2)[win], r=r, spacing=(1.0 / n, 1.0 / n),
+                      sources=[OP.Source(local, 9.0, 0.1, 50.0)])
+    part = G.macro_step(opw, 0.09, y0[(slice(None),) + win], H, steps, c)
+    k = hw - reach                                       # exact half-width: 4
+    inner = (slice(None), slice(hw - k, hw + k + 1), slice(hw - k, hw + k + 1))
+    want = full[(slice(None),) + np.ix_(iy[hw - k:hw + k + 1], ix[hw - k:hw + k + 1])]
+    assert np.array_equal(part[inner], want)
+    # while near the window's edge its wrap has changed the values
+    edge = full[(slice(None),) + np.ix_(iy[:8], ix)]
+    assert np.abs(part[:, :8, :] - edge).max() > 1e-3 * np.abs(edge).max()
