@@ -1,7 +1,9 @@
 """GPU batching: instances of uneven size advanced together must equal the
 same instances advanced one by one (bitwise: same kernels, same arithmetic),
 and the oracle; the captured graph must equal eager launches on every
-replay."""
+replay; and the batch workload at its full size (64 instances, 256^2 to
+1024^2, autotuned and graph-captured as the benchmark runs it) against the
+oracle, whole or on periodic windows around sampled points."""
 import numpy as np
 import pytest
 import torch
@@ -107,3 +109,49 @@ def test_batch_autotune_picks_a_candidate():
     other.step(ref, n_macro=1)
     for a, b in zip(ys, ref):
         assert rel_err(a.cpu().numpy(), b.cpu().numpy(), 1) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 3e-5)])
+def test_full_size_batch_vs_oracle(dtype, tol):
+    # the batch workload itself in the benchmark's launch configuration (64
+    # instances of 256^2 .. 1024^2 with their log-normal c^2 and H,
+    # autotuned variant and band, graph-captured), one macro step from random
+    # states: every 256^2 instance whole against the oracle, and each larger
+    # instance sampled, the oracle on two periodic windows of half-width 30
+    # with the instance's spacing, exact at the 9^2 points within 4 of the
+    # middle (the longest sequence's 13 evaluations reach 13 x 2 = 26 points;
+    # FP32 stepping held to the bound u32 sum|c| (1 + sum N_j))
+    sch = schemes.ORDER8_K6
+    steps, c = oracle_weights(sch)
+    _, w, _ = scheme_weights(sch)
+    inst = workloads.batch_instances(workloads.CONFIG_BATCH)
+    rng = np.random.default_rng(64)
+    y0 = [rng.standard_normal((3, n, n)) for n, _, _ in inst]
+    spec = [dict(n=(n, n), H=H, c2_field=to_dev(cs * cs, dtype), c_max=float(cs.max()))
+            for n, cs, H in inst]
+    batch = GBSBatch(spec, 8, steps, w, dtype=dtype)
+    batch.autotune([to_dev(a[None], dtype) for a in y0], macro_steps=1)
+    batch.set_graph(True)
+    ys = [to_dev(a[None], dtype) for a in y0]
+    batch.step(ys, n_macro=1)
+    hw, k = 30, 4
+    whole = 0
+    for i, ((n, cs, H), a, y) in enumerate(zip(inst, y0, ys)):
+        got = y[0]
+        if n == 256:
+            want = G.macro_step(OP.Acoustic((n, n), c2=cs * cs, r=2), 0.0, a, H, steps, c)
+            e = rel_err(got.double().cpu().numpy(), want, 0)
+            whole += 1
+            assert e <= tol, (i, n, e)
+            continue
+        for ctr in (tuple(int(v) for v in rng.integers(0, n, size=2)), (1, n - 2)):
+            iy, ix = [np.arange(q - hw, q + hw + 1) % n for q in ctr]
+            op = OP.Acoustic((2 * hw + 1,) * 2, c2=(cs * cs)[np.ix_(iy, ix)], r=2,
+                             spacing=(1.0 / n, 1.0 / n))
+            want = G.macro_step(op, 0.0, a[(slice(None),) + np.ix_(iy, ix)], H, steps, c)
+            want = want[:, hw - k:hw + k + 1, hw - k:hw + k + 1]
+            ty, tx = [torch.from_numpy(v[hw - k:hw + k + 1]).cuda() for v in (iy, ix)]
+            part = got[:, ty[:, None], tx[None, :]].double().cpu().numpy()
+            e = rel_err(part, want, 0)
+            assert e <= tol, (i, n, ctr, e)
+    assert whole > 0
