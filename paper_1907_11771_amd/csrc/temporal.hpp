@@ -648,15 +648,34 @@ struct CombineArgs {
   int32_t k;
 };
 
+// sum_j c[j] ystar[j][i] over j = 0..k-1 in ascending j.  The loads of up to
+// COMBINE_CHUNK sequences are issued together before the sum uses them (a
+// loop over the runtime k alone waits for each load before issuing the
+// next); the sum itself keeps the order.  Each y* is read once: non-temporal
+// loads keep them from displacing y_out, which the next macro step's first
+// passes read.
+constexpr int COMBINE_CHUNK = 8;
+
+__device__ __forceinline__ double combine_point(const double* const* ystar, const double* c,
+                                                int k, int64_t i) {
+  double v = 0.0;
+  for (int j0 = 0; j0 < k; j0 += COMBINE_CHUNK) {
+    double y[COMBINE_CHUNK];
+#pragma unroll
+    for (int u = 0; u < COMBINE_CHUNK; ++u)
+      y[u] = j0 + u < k ? __builtin_nontemporal_load(ystar[j0 + u] + i) : 0.0;
+#pragma unroll
+    for (int u = 0; u < COMBINE_CHUNK; ++u)
+      if (j0 + u < k) v = j0 + u == 0 ? c[0] * y[u] : v + c[j0 + u] * y[u];
+  }
+  return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void combine_kernel(const CombineArgs<T> a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  // each y* is read once: non-temporal loads keep them from displacing
-  // y_out, which the next macro step's first passes read
-  double v = a.c[0] * __builtin_nontemporal_load(a.ystar[0] + i);
-  for (int j = 1; j < a.k; ++j) v = v + a.c[j] * __builtin_nontemporal_load(a.ystar[j] + i);
-  a.yout[i] = (T)v;
+  a.yout[i] = (T)combine_point(a.ystar, a.c, a.k, i);
 }
 
 // The same for a batch: block b belongs to the instance whose first block is
@@ -684,9 +703,7 @@ __global__ __launch_bounds__(256) void combine_batch(const CombineItem<T>* items
   const CombineItem<T>* it = items + lo;
   const int64_t i = (int64_t)(b - it->block_begin) * blockDim.x + threadIdx.x;
   if (i >= it->n) return;
-  double v = it->c[0] * __builtin_nontemporal_load(it->ystar[0] + i);
-  for (int j = 1; j < it->k; ++j) v = v + it->c[j] * __builtin_nontemporal_load(it->ystar[j] + i);
-  it->yout[i] = (T)v;
+  it->yout[i] = (T)combine_point(it->ystar, it->c, it->k, i);
 }
 
 }  // namespace gbs
