@@ -2063,21 +2063,47 @@ struct AdjSumArgs {
   int32_t k, nrhs;
 };
 
+// The sums run in ascending sequence order (and right-hand side order for
+// the gradient); the loads of up to 8 terms are issued before they are
+// added, since a loop over the runtime count alone waits for each load.
 template <typename T>
 __global__ __launch_bounds__(256) void adj_sum_kernel(const AdjSumArgs<T> a) {
+  constexpr int CH = 8;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  double ys = a.ysum[0][i], fs = a.f1[0][i];
-  for (int r = 1; r < a.k; ++r) {
-    ys += a.ysum[r][i];
-    fs += a.f1[r][i];
+  double ys = 0.0, fs = 0.0;
+  for (int r0 = 0; r0 < a.k; r0 += CH) {
+    double y[CH], f[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      y[u] = r0 + u < a.k ? a.ysum[r0 + u][i] : 0.0;
+      f[u] = r0 + u < a.k ? a.f1[r0 + u][i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (r0 + u < a.k) {
+        ys = r0 + u == 0 ? y[u] : ys + y[u];
+        fs = r0 + u == 0 ? f[u] : fs + f[u];
+      }
+    }
   }
   a.yacc[i] = ys;
   a.facc[i] = fs;
   if (a.grad && i < a.field) {
+    // terms t = r nrhs + q: sequence r, right-hand side q
+    const int nt = a.k * a.nrhs;
     double gs = 0.0;
-    for (int r = 0; r < a.k; ++r)
-      for (int q = 0; q < a.nrhs; ++q) gs += a.gsum[r][(int64_t)q * a.field + i];
+    for (int t0 = 0; t0 < nt; t0 += CH) {
+      double g[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int t = t0 + u;
+        g[u] = t < nt ? a.gsum[t / a.nrhs][(int64_t)(t % a.nrhs) * a.field + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (t0 + u < nt) gs += g[u];
+    }
     a.grad[i] += gs;
   }
 }
