@@ -205,9 +205,9 @@ void adj_pass2d(const AdjPassArgs<T> a) {
         if (sl < 0) sl += CQ;
         T c2 = a.c2c;
         if constexpr (VARC) c2 = myq[sl * 64];
-        int row = 0;
-        if (srcs || e == g) row = wrap_sub(irow, e * S, ny);
-        const int64_t pt = (int64_t)row * nx + gx;
+        // the row of this level's point, formed only where a source term or
+        // the pass's stores need it
+        auto level_row = [&]() { return wrap_sub(irow, e * S, ny); };
         // forward operator on Y (for the reversal), M on Psi
         const T dvx = invx * sxv;
         const T dvy = invy * sy[1];
@@ -216,10 +216,12 @@ void adj_pass2d(const AdjPassArgs<T> a) {
         fy[1] = -(invx * sxp);
         fy[2] = -(invy * sy[0]);
         if (srcs) {
+          const int row = level_row();
           if (ls.count == 1) {
             if (row == ls.row) fy[0] += (T)(ls.w * d.amp[e - 1]);
           } else if (ls.count > 1) {
-            fy[0] += source_term<T>(a.src_dev, a.g.nsrc, blockIdx.z, pt, d.amp[e - 1]);
+            fy[0] += source_term<T>(a.src_dev, a.g.nsrc, blockIdx.z, (int64_t)row * nx + gx,
+                                    d.amp[e - 1]);
           }
         }
         fm[0] = c2 * (invx * sxL + invy * sy[3]);
@@ -248,6 +250,7 @@ void adj_pass2d(const AdjPassArgs<T> a) {
         }
         if (e == g) {
           const int yo = i0 + k - e * S;
+          const int64_t pt = (int64_t)level_row() * nx + gx;
           const bool store = lane_ok && yo >= ya && yo < yb;
           if (store) {
             if (!final_) {

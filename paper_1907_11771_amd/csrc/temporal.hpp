@@ -119,10 +119,14 @@ __device__ __forceinline__ T lane_dsum(T u) {
   return s;
 }
 
-// r - d wrapped into [0, n) for 0 <= r < n, d >= 0 (wave-uniform operands)
+// r - d wrapped into [0, n) for 0 <= r < n, d >= 0 (wave-uniform operands);
+// one addition when d <= n, the common case
 __device__ __forceinline__ int wrap_sub(int r, int d, int n) {
   r -= d;
-  while (r < 0) r += n;
+  if (r < 0) {
+    r += n;
+    while (r < 0) r += n;
+  }
   return r;
 }
 
@@ -348,9 +352,9 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
           sxp = lane_dsum<T, ORDER>(In[c][0]);
           sxv = lane_dsum<T, ORDER>(In[c][1]);
         }
-        int row = 0;
-        if (srcs || e == g) row = wrap_sub(irow, e * S, ny);
-        const int64_t pt = (int64_t)row * nx + gx;
+        // the row of this level's point and its flat index, formed only
+        // where a source term or the pass's stores need them
+        auto level_row = [&]() { return wrap_sub(irow, e * S, ny); };
         T c2 = w.c2c;
         if constexpr (VARC) {
           int sl = kq - e * S;
@@ -364,10 +368,11 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
         f[1] = -(w.invx * sxp);
         f[2] = -(w.invy * syp);
         if (srcs) {
+          const int row = level_row();
           if (ls.count == 1) {
             if (row == ls.row) f[0] += (T)(ls.w * w.amp[e - 1]);
           } else if (ls.count > 1) {
-            f[0] += source_term<T>(w.src, w.nsrc, w.rhs, pt, w.amp[e - 1]);
+            f[0] += source_term<T>(w.src, w.nsrc, w.rhs, (int64_t)row * nx + gx, w.amp[e - 1]);
           }
         }
         T nw[3];
@@ -386,6 +391,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
         if (e == g) {
           // the pass's last level, at row i - g S
           const int yo = i0 + k - e * S;
+          const int64_t pt = (int64_t)level_row() * nx + gx;
           if (lane_ok && yo >= ya && yo < yb) {
             if (!final_) {
 #pragma unroll
