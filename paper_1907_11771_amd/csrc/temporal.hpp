@@ -20,8 +20,9 @@
 // input level) is produced e*R rows behind the input front (time skew), so
 // that every stencil input of A_e already exists.  Each lane keeps, for
 // every level, the last 2R+1 rows of (p, v_x, v_y) of its column in
-// registers (y-neighbours); x-neighbours come from the adjacent lanes by
-// cross-lane moves.  The lanes next to the strip edges receive no valid
+// registers (y-neighbours); x-neighbours come from the adjacent lanes, by
+// cross-lane moves (v_x) and through a row in LDS that the wavefront writes
+// and reads back (p).  The lanes next to the strip edges receive no valid
 // neighbour data, so A_e is exact only on lanes [e*R, 64 - e*R): a pass of
 // g evaluations stores the 64 - 2 g R inner columns, and consecutive strips
 // overlap by 2 g R columns.
@@ -38,6 +39,9 @@ constexpr int PASS_KEEP = 4;    // final pass also stores (y_{N-1}, y_N) to out_
 constexpr int PASS_F0 = 8;      // first pass of the shared form: old = y_0, cur = y_0 + h F_0
 constexpr int PASS_COMBINE = 16;  // final pass stores y_out = sum_j c_j y*_j (COMB kernels)
 constexpr int PASS_GMAX = 8;
+// the x-derivative of p from an LDS row of the wavefront instead of lane
+// moves (WPG = 1 passes)
+constexpr bool PASS_XLDS = true;
 constexpr int COMB_MAX = 5;     // y* of other sequences a combining pass reads per point
 
 template <typename T>
@@ -271,6 +275,10 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
   __shared__ T c2q[VARC ? NWQ : 1][VARC ? CQ : 1][64];
   const int wq = WPG > 1 ? wave : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   T* const myq = &c2q[VARC ? wq : 0][0][lane];
+  // one row of p per wavefront for the x-neighbours (PASS_XLDS), R entries
+  // of padding on each side feed only the discarded edge lanes
+  __shared__ T xrows[PASS_XLDS && WPG == 1 ? 4 : 1][PASS_XLDS && WPG == 1 ? 64 + 2 * R : 1];
+  T* const xrow = &xrows[PASS_XLDS && WPG == 1 ? wq : 0][PASS_XLDS && WPG == 1 ? R : 0];
   if constexpr (VARC) {
     for (int s = 1; s < CQ; ++s) myq[(CQ - s) * 64] = w.c2f[(int64_t)pmod(i0 - s, ny) * nx + gx];
   }
@@ -348,6 +356,28 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
                                           &ring.v[rslot][rw][e - 1][0][0], has_left, has_right);
           sxv = lane_dsum_edges<T, ORDER>(In[c][1], lane, &ring.v[rslot][lw][e - 1][1][R],
                                           &ring.v[rslot][rw][e - 1][1][0], has_left, has_right);
+        } else if constexpr (PASS_XLDS) {
+          // p's x-neighbours through this wavefront's LDS row, v_x's by lane
+          // moves: half the cross-lane traffic leaves the vector ALU.  The
+          // row is written and read by one wavefront, whose LDS operations
+          // execute in order, so no barrier; the wave barriers keep the
+          // compiler from moving the other lanes' reads across the write (or
+          // the next level's write across these reads), which a single
+          // thread's view of the addresses would allow.
+          xrow[lane] = In[c][0];
+          __builtin_amdgcn_wave_barrier();
+          T xn[2 * R];
+#pragma unroll
+          for (int kk = 0; kk < R; ++kk) {
+            xn[2 * kk] = xrow[lane + kk + 1];
+            xn[2 * kk + 1] = xrow[lane - kk - 1];
+          }
+          __builtin_amdgcn_wave_barrier();
+          sxp = Fd<ORDER>::template w<T>(0) * (xn[0] - xn[1]);
+#pragma unroll
+          for (int kk = 1; kk < R; ++kk)
+            sxp += Fd<ORDER>::template w<T>(kk) * (xn[2 * kk] - xn[2 * kk + 1]);
+          sxv = lane_dsum<T, ORDER>(In[c][1]);
         } else {
           sxp = lane_dsum<T, ORDER>(In[c][0]);
           sxv = lane_dsum<T, ORDER>(In[c][1]);
