@@ -40,8 +40,10 @@ constexpr int PASS_F0 = 8;      // first pass of the shared form: old = y_0, cur
 constexpr int PASS_COMBINE = 16;  // final pass stores y_out = sum_j c_j y*_j (COMB kernels)
 constexpr int PASS_GMAX = 8;
 // the x-derivative of p from an LDS row of the wavefront instead of lane
-// moves (WPG = 1 passes)
-constexpr bool PASS_XLDS = true;
+// moves (WPG = 1 passes, FP64, where a lane move of one value takes two
+// 32-bit moves)
+template <typename T>
+constexpr bool pass_xlds() { return sizeof(T) == 8; }
 constexpr int COMB_MAX = 5;     // y* of other sequences a combining pass reads per point
 
 template <typename T>
@@ -275,10 +277,11 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
   __shared__ T c2q[VARC ? NWQ : 1][VARC ? CQ : 1][64];
   const int wq = WPG > 1 ? wave : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   T* const myq = &c2q[VARC ? wq : 0][0][lane];
-  // one row of p per wavefront for the x-neighbours (PASS_XLDS), R entries
+  // one row of p per wavefront for the x-neighbours (pass_xlds), R entries
   // of padding on each side feed only the discarded edge lanes
-  __shared__ T xrows[PASS_XLDS && WPG == 1 ? 4 : 1][PASS_XLDS && WPG == 1 ? 64 + 2 * R : 1];
-  T* const xrow = &xrows[PASS_XLDS && WPG == 1 ? wq : 0][PASS_XLDS && WPG == 1 ? R : 0];
+  constexpr bool XL = pass_xlds<T>() && WPG == 1;
+  __shared__ T xrows[XL ? 4 : 1][XL ? 64 + 2 * R : 1];
+  T* const xrow = &xrows[XL ? wq : 0][XL ? R : 0];
   if constexpr (VARC) {
     for (int s = 1; s < CQ; ++s) myq[(CQ - s) * 64] = w.c2f[(int64_t)pmod(i0 - s, ny) * nx + gx];
   }
@@ -356,7 +359,7 @@ __device__ __forceinline__ void pass_body(const PassWork<T> w, const int strip, 
                                           &ring.v[rslot][rw][e - 1][0][0], has_left, has_right);
           sxv = lane_dsum_edges<T, ORDER>(In[c][1], lane, &ring.v[rslot][lw][e - 1][1][R],
                                           &ring.v[rslot][rw][e - 1][1][0], has_left, has_right);
-        } else if constexpr (PASS_XLDS) {
+        } else if constexpr (pass_xlds<T>()) {
           // p's x-neighbours through this wavefront's LDS row, v_x's by lane
           // moves: half the cross-lane traffic leaves the vector ALU.  The
           // row is written and read by one wavefront, whose LDS operations
