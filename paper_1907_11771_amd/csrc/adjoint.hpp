@@ -97,6 +97,7 @@ struct AdjArgs {
   int32_t last;         // this step is n = 1: fold into yacc / facc
   int32_t first_seq;    // the first sequence writes yacc / facc instead of adding
   int32_t nrhs;         // right-hand sides (looped over by each thread)
+  int32_t tz;           // adj_tile3d: planes per block (0: the template's TZ)
 };
 
 // Step n = N of sequence j: reads w = c_j ybar at the neighbours, writes
@@ -343,14 +344,15 @@ void adj_tile3d(const AdjArgs<T> a) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
   const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
-  const int x0 = tx * BX, y0 = ty * BY, z0 = tz * TZ;
+  const int tzn = a.tz > 0 ? a.tz : TZ;              // planes per block
+  const int x0 = tx * BX, y0 = ty * BY, z0 = tz * tzn;
   const int x = x0 + lx, y = y0 + ly;
   const bool valid = x < (int)nx && y < (int)ny;
   const uint32_t F1 = (uint32_t)a.g.field;
   const uint32_t plane = nx * ny;
   const uint32_t own = (uint32_t)pmod(y, ny) * nx + (uint32_t)pmod(x, nx);
   const uint32_t pil = (uint32_t)y * nx + (uint32_t)x;
-  const int zend = min(z0 + TZ, nz);
+  const int zend = min(z0 + tzn, nz);
   const T h2 = (T)(2.0 * a.h);
   const T cq = (T)(0.25 * a.cw), ch = (T)(0.5 * a.cw);
   const T* __restrict__ c2f = a.c2f;

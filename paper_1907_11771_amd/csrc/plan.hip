@@ -2322,9 +2322,34 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
   // were slower than the z-marching sweeps)
   const bool tiled = OP == OP_AC3D && v == GBS_VARIANT_TILE3D;
   constexpr int ATZ = 128, ABY = sizeof(T) == 4 ? 12 : 8, AWPE = sizeof(T) == 4 ? 3 : 2;
-  const unsigned tblocks = (unsigned)(((P->prob.n[0] + 63) / 64) *
-                                      ((P->prob.n[1] + ABY - 1) / ABY) *
-                                      ((P->prob.n[2] + ATZ - 1) / ATZ));
+  // planes per block of the tiled sweeps: a sweep runs its blocks in rounds
+  // of the blocks the GPU holds at once (one per CU), so the z-chunking is
+  // the one that minimises rounds x (planes + the 2R warm-up planes of a
+  // chunk); 384^3 FP32: 96 planes (768 blocks, 3 rounds) rather than 128
+  // (576 blocks: a third round a quarter full)
+  unsigned tblocks = 0;
+  int atz = ATZ;
+  if (OP == OP_AC3D && tiled) {
+    constexpr int RA = Fd<ORDER>::R;
+    const long txy = (long)((P->prob.n[0] + 63) / 64) * (long)((P->prob.n[1] + ABY - 1) / ABY);
+    const int nz = (int)P->prob.n[2];
+    const int waves = resident_waves(adj_tile3d<T, ORDER, ATZ, ABY, false, true, AWPE>, 64 * ABY);
+    const long slots = std::max(1, waves / ABY);
+    double best = 1e300;
+    int prev = 0;
+    for (int m = 1; m <= std::max(1, nz / 16); ++m) {
+      const int tz = (nz + m - 1) / m;
+      if (tz == prev) continue;
+      prev = tz;
+      const long blocks = txy * ((nz + tz - 1) / tz);
+      const double cost = (double)((blocks + slots - 1) / slots) * (double)(tz + 2 * RA);
+      if (cost < best * (1.0 - 1e-9)) {
+        best = cost;
+        atz = tz;
+      }
+    }
+    tblocks = (unsigned)(txy * ((nz + atz - 1) / atz));
+  }
 
   if (tbar && P->nrec)
     hipLaunchKernelGGL(inject_kernel<T>, dim3((unsigned)((P->nrec + 255) / 256)), dim3(256), 0, s,
@@ -2350,6 +2375,7 @@ int adjoint_run(gbs_plan* P, double t0, const T* y0, T* ybar, const T* tbar, dou
   aa.facc = facc;
   aa.grad = grad;
   aa.nrhs = P->prob.n_rhs;
+  aa.tz = atz;
   auto adj_sweep = [&](bool first) {
     if constexpr (OP == OP_AC3D) {
       if (tiled) {
