@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
 
 // 3-D acoustic sweeps with the x/y neighbourhood of every plane staged in
 // LDS.  A 1024-thread block covers a 64 x 16 tile of (x, y) columns and
-// marches up TZ planes; every thread keeps the planes z-R..z+R of p and v_z
+// marches up tzn planes; every thread keeps the planes z-R..z+R of p and v_z
 // of its column in registers (the z-derivatives).  Per plane the block
 // writes p, v_x and v_y of its tile, with the R-wide halo of p and v_x along
 // x and of p and v_y along y, to LDS once (two buffers, one barrier per
@@ -332,10 +332,10 @@ __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
 // column, the flat index, the velocity derivatives, f_v (f[1..3]) and the
 // plane's four values.  (Loading the point's other inputs a plane ahead
 // needs registers that make the sweep spill.)
-template <typename T, int ORDER, int TZ, typename Point>
+template <typename T, int ORDER, typename Point>
 __device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geometry& g,
                                              T invx, T invy, T invz, const int tile,
-                                             Point point) {
+                                             const int tzn, Point point) {
   constexpr int R = Fd<ORDER>::R;
   constexpr int BX = 64, BY = 16, LX = BX + 2 * R, LY = BY + 2 * R;
   constexpr int NYH = 2 * R * BX * 2;          // y-halo values (p, v_y) per plane
@@ -348,7 +348,7 @@ __device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geo
   const int ntx = (nx + BX - 1) / BX, nty = (ny + BY - 1) / BY;
   const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
   const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
-  const int x0 = tx * BX, y0 = ty * BY, z0 = tz * TZ;
+  const int x0 = tx * BX, y0 = ty * BY, z0 = tz * tzn;
   const int x = x0 + lx, y = y0 + ly;
   const bool valid = x < nx && y < ny;
   const int64_t F1 = g.field;
@@ -386,7 +386,7 @@ __device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geo
     pw[k] = cp[e];
     vw[k] = cvz[e];
   }
-  const int zend = min(z0 + TZ, nz);
+  const int zend = min(z0 + tzn, nz);
   const int64_t pil = (int64_t)y * nx + x;         // valid columns only
   T vxo, vyo, hyv = T(0), hxv = T(0);
   {
@@ -459,10 +459,9 @@ __device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geo
 template <typename T>
 constexpr int tile3d_waves() { return sizeof(T) == 4 ? 8 : 4; }
 
-// Tiles of the 64 x 16 x TZ blocking of lf_tile3d / first_tile3d.
-template <int TZ>
-__device__ __forceinline__ int tile3d_count(const Geometry& g) {
-  return ((g.nx + 63) / 64) * ((g.ny + 15) / 16) * ((g.nz + TZ - 1) / TZ);
+// Tiles of the 64 x 16 x tzn blocking of lf_tile3d / first_tile3d.
+__device__ __forceinline__ int tile3d_count(const Geometry& g, int tzn) {
+  return ((g.nx + 63) / 64) * ((g.ny + 15) / 16) * ((g.nz + tzn - 1) / tzn);
 }
 
 // Workgroup index -> (tile, sequence) for a launch of n sequences over
@@ -483,15 +482,16 @@ __device__ __forceinline__ void xcd_tile_seq(int b, int tiles, int n, int& tile,
 template <typename T, int ORDER, int TZ>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(tile3d_waves<T>())))
 void lf_tile3d(const StepArgs<T> a) {
-  const int tiles = tile3d_count<TZ>(a.g);
+  const int tzn = a.tz > 0 ? a.tz : TZ;
+  const int tiles = tile3d_count(a.g, tzn);
   int tile, sq;
   xcd_tile_seq(blockIdx.x, tiles, gridDim.x / tiles, tile, sq);
   const SeqDesc<T>& d = a.seq[sq];
   const int64_t rhs = blockIdx.z;
   const int64_t base = rhs * a.g.state;
   const int64_t F1 = a.g.field;
-  tile3d_march<T, ORDER, TZ>(
-      d.cur + base, a.g, a.invx, a.invy, a.invz, tile,
+  tile3d_march<T, ORDER>(
+      d.cur + base, a.g, a.invx, a.invy, a.invz, tile, tzn,
       [&](int64_t idx, T dvx, T dvy, T dvz, T* f, const T* c) {
         const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
         f[0] = -(c2 * ((dvx + dvy) + dvz));
@@ -523,8 +523,9 @@ void first_tile3d(const FirstArgs<T> a) {
   const int64_t rhs = blockIdx.z;
   const int64_t base = rhs * a.g.state;
   const int64_t F1 = a.g.field;
-  tile3d_march<T, ORDER, TZ>(
+  tile3d_march<T, ORDER>(
       a.y0 + base, a.g, a.invx, a.invy, a.invz, xcd_tile(blockIdx.x, gridDim.x),
+      a.tz > 0 ? a.tz : TZ,
       [&](int64_t idx, T dvx, T dvy, T dvz, T* f, const T* c) {
         const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
         f[0] = -(c2 * ((dvx + dvy) + dvz));

@@ -737,22 +737,54 @@ void launch_march3d(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gz) {
                      0, P->stream, sa);
 }
 
-// LDS-tiled 3-D sweeps: 64 x 16 columns per 1024-thread block, TILE_TZ planes
+// LDS-tiled 3-D sweeps: 64 x 16 columns per 1024-thread block, at most
+// TILE_TZ planes per block
 constexpr int TILE_TZ = 128;
 
-unsigned tile3d_blocks(const gbs_plan* P) {
+unsigned tile3d_blocks(const gbs_plan* P, int tz) {
   const int ntx = (int)((P->prob.n[0] + 63) / 64);
   const int nty = (int)((P->prob.n[1] + 15) / 16);
-  const int ntz = (int)((P->prob.n[2] + TILE_TZ - 1) / TILE_TZ);
+  const int ntz = (int)((P->prob.n[2] + tz - 1) / tz);
   return (unsigned)(ntx * nty * ntz);
+}
+
+// Planes per block of an LDS-tiled sweep launch with `mult` blocks per tile
+// (sequences x right-hand sides): its blocks run in rounds of the blocks the
+// GPU holds at once, so the chunking (at most TILE_TZ planes) is the one that
+// minimises rounds x (planes + the 2R warm-up planes of a chunk).  A launch
+// of many blocks keeps TILE_TZ; one of a few rounds (one sequence, few
+// right-hand sides) gets shorter chunks so that its last round is not
+// mostly idle.
+template <int ORDER, typename K>
+int tile3d_planes(const gbs_plan* P, K kernel, long mult) {
+  constexpr int R = Fd<ORDER>::R;
+  const long txy = (long)((P->prob.n[0] + 63) / 64) * (long)((P->prob.n[1] + 15) / 16);
+  const int nz = (int)P->prob.n[2];
+  const long slots = std::max(1, resident_waves(kernel, 1024) / 16);
+  int best_tz = std::min(TILE_TZ, nz), prev = 0;
+  double best = 1e300;
+  for (int m = (nz + TILE_TZ - 1) / TILE_TZ; m <= std::max(1, nz / 16); ++m) {
+    const int tz = (nz + m - 1) / m;
+    if (tz == prev) continue;
+    prev = tz;
+    const long blocks = txy * ((nz + tz - 1) / tz) * mult;
+    const double cost = (double)((blocks + slots - 1) / slots) * (double)(tz + 2 * R);
+    if (cost < best * (1.0 - 1e-9)) {
+      best = cost;
+      best_tz = tz;
+    }
+  }
+  return best_tz;
 }
 
 template <typename T, int ORDER, int OP>
 void launch_first(gbs_plan* P, const FirstArgs<T>& fa, unsigned gx, unsigned gz) {
   if constexpr (OP == OP_AC3D && ORDER != GBS_FD_SPECTRAL) {
     if (resolve_variant(P) == GBS_VARIANT_TILE3D) {
-      hipLaunchKernelGGL((first_tile3d<T, ORDER, TILE_TZ>), dim3(tile3d_blocks(P), 1, gz),
-                         dim3(1024), 0, P->stream, fa);
+      FirstArgs<T> a = fa;
+      a.tz = tile3d_planes<ORDER>(P, first_tile3d<T, ORDER, TILE_TZ>, (long)gz);
+      hipLaunchKernelGGL((first_tile3d<T, ORDER, TILE_TZ>), dim3(tile3d_blocks(P, a.tz), 1, gz),
+                         dim3(1024), 0, P->stream, a);
       return;
     }
   }
@@ -774,8 +806,10 @@ template <typename T, int ORDER, int OP>
 void launch_lf(gbs_plan* P, const StepArgs<T>& sa, int n, unsigned gx, unsigned gz) {
   if constexpr (OP == OP_AC3D && ORDER != GBS_FD_SPECTRAL) {
     if (resolve_variant(P) == GBS_VARIANT_TILE3D) {
-      hipLaunchKernelGGL((lf_tile3d<T, ORDER, TILE_TZ>), dim3(tile3d_blocks(P) * n, 1, gz),
-                         dim3(1024), 0, P->stream, sa);
+      StepArgs<T> a = sa;
+      a.tz = tile3d_planes<ORDER>(P, lf_tile3d<T, ORDER, TILE_TZ>, (long)n * gz);
+      hipLaunchKernelGGL((lf_tile3d<T, ORDER, TILE_TZ>), dim3(tile3d_blocks(P, a.tz) * n, 1, gz),
+                         dim3(1024), 0, P->stream, a);
       return;
     }
   }

@@ -204,6 +204,7 @@ struct StepArgs {
   const T* c2f;    // coefficient field or null
   T c2c;           // constant coefficient
   T invx, invy, invz;
+  int32_t tz;      // LDS-tiled 3-D sweeps: planes per block (0: the kernel's TZ)
 };
 
 template <typename T>
@@ -217,6 +218,7 @@ struct FirstArgs {
   T c2c;
   T invx, invy, invz;
   int32_t nseq;
+  int32_t tz;            // LDS-tiled 3-D sweeps: planes per block (0: the kernel's TZ)
   double amp;            // source wavelet at t_0
 };
 
