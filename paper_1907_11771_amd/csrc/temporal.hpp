@@ -21,8 +21,8 @@
 // that every stencil input of A_e already exists.  Each lane keeps, for
 // every level, the last 2R+1 rows of (p, v_x, v_y) of its column in
 // registers (y-neighbours); x-neighbours come from the adjacent lanes, by
-// cross-lane moves (v_x) and through a row in LDS that the wavefront writes
-// and reads back (p).  The lanes next to the strip edges receive no valid
+// cross-lane moves, and in FP64 p's through a row in LDS that the wavefront
+// writes and reads back.  The lanes next to the strip edges receive no valid
 // neighbour data, so A_e is exact only on lanes [e*R, 64 - e*R): a pass of
 // g evaluations stores the 64 - 2 g R inner columns, and consecutive strips
 // overlap by 2 g R columns.
