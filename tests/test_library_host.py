@@ -112,7 +112,8 @@ def test_plan_rejects_order_2_mod_4_and_bad_weights():
     assert e.value.status == B.GBS_EORDER
 
 
-@pytest.mark.parametrize("kw", [dict(n=(4, 64)), dict(n=(64, 64), fd_order=6),
+@pytest.mark.parametrize("kw", [dict(n=(4, 64)), dict(n=(64, 8), fd_order=8),
+                                dict(n=(64, 64), fd_order=6),
                                 dict(n=(64, 64), n_rhs=0), dict(n=(64, 64), dtype=7),
                                 dict(n=(64, 64), c2=-1.0)])
 def test_plan_rejects_bad_problem(kw):
