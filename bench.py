@@ -237,12 +237,13 @@ def batch_inputs():
     return inst, y0
 
 
-def batch_leg(n_macro, warmup, dtype_name, plain=True, inputs=None):
+def batch_leg(n_macro, warmup, dtype_name, plain=True, inputs=None, pin=None):
     """64 uneven instances advanced in one batch (graph-replayed macro steps,
-    autotuned variant and band) for ``n_macro`` timed macro steps, in FP64 or
-    FP32 stepping (then with the error against the FP64 batch after the same
-    steps), and the plain FP64 form (one streaming launch per sequence per
-    leap-frog step, instance by instance) per macro step."""
+    autotuned variant and band, or the (variant, band) ``pin``) for
+    ``n_macro`` timed macro steps, in FP64 or FP32 stepping (then with the
+    error against the FP64 batch after the same steps), and the plain FP64
+    form (one streaming launch per sequence per leap-frog step, instance by
+    instance) per macro step."""
     import torch
     from paper_1907_11771_amd import binding as B
     from paper_1907_11771_amd.plan import GBSBatch, GBSPlan, scheme_weights
@@ -256,9 +257,13 @@ def batch_leg(n_macro, warmup, dtype_name, plain=True, inputs=None):
     spec = [dict(n=(n, n), H=H, c2_field=torch.from_numpy(c * c).to(dev), c_max=float(c.max()))
             for n, c, H in inst]
     batch = GBSBatch(spec, 8, steps, w, dtype=dtype, device=dev)
-    tune = [torch.from_numpy(a).to(dev, dtype) for a in y0]
-    variant, band = batch.autotune(tune, macro_steps=1)
-    del tune
+    if pin:
+        variant, band = pin
+        batch.set_variant(variant, band)
+    else:
+        tune = [torch.from_numpy(a).to(dev, dtype) for a in y0]
+        variant, band = batch.autotune(tune, macro_steps=1)
+        del tune
     batch.set_graph(True)
     ys = [torch.from_numpy(a).to(dev, dtype) for a in y0]
     batch.step(ys, n_macro=max(warmup, 1))
@@ -280,6 +285,31 @@ def batch_leg(n_macro, warmup, dtype_name, plain=True, inputs=None):
         ref.step(yr, n_macro=n_macro)
         err = max(float((a.double() - b).abs().max() / b.abs().max()) for a, b in zip(ys, yr))
         del ref, yr
+
+    # method bytes of one macro step (the passes and the combination of every
+    # instance), as a single plan of the instance's size and the batch's
+    # variant counts them
+    step_bytes, pass_launches = 0.0, 0
+    for n in sorted(set(n for n, _, _ in inst)):
+        same = [(c, H) for m, c, H in inst if m == n]
+        c, H = same[0]
+        pl = GBSPlan(B.ACOUSTIC2D, (n, n), 8, steps, w, H, dtype=dtype,
+                     c2_field=torch.from_numpy(c * c).to(dev), c_max=float(c.max()), device=dev)
+        pl.set_variant(variant)
+        sb, pass_launches, ab, _ = pl.algorithmic_bytes()
+        step_bytes += len(same) * (sb + ab)
+        del pl
+    # measured HBM bytes of a macro step, where a counter summary of the
+    # batch's pass and combination kernels was taken on the current sources
+    forms = {B.VARIANT_TEMPORAL: "7, false, 1", B.VARIANT_TEMPORAL4: "4, false, 1",
+             B.VARIANT_TEMPORAL_S5: "5, true, 1", B.VARIANT_TEMPORAL_S6: "6, true, 1",
+             B.VARIANT_TEMPORAL_WG4: "7, false, 4", B.VARIANT_TEMPORAL_WG8: "7, false, 8"}
+    tname = "double" if dtype == torch.float64 else "float"
+    kpass = "gbs::pass2d_batch<%s, 4, %s>" % (tname, forms.get(variant, "?"))
+    tp = measured_traffic(kpass, cfg["name"])
+    tc = measured_traffic("gbs::combine_batch<%s>" % tname, cfg["name"])
+    traffic_bytes = (pass_launches * tp["bytes_per_launch"] + tc["bytes_per_launch"]
+                     if tp and tc else None)
 
     # the plain FP64 form on the same instances (a few macro steps, per macro step)
     plain_ms = None
@@ -309,10 +339,18 @@ def batch_leg(n_macro, warmup, dtype_name, plain=True, inputs=None):
         config=dict(workload=cfg["name"], instances=len(inst),
                     sizes=sorted(set(n for n, _, _ in inst)), points=sum(n * n for n, _, _ in inst),
                     evals_per_macro_step=1 + sum(steps), graph=True,
-                    autotuned=dict(variant=variant, band=band)),
+                    **{"pinned" if pin else "autotuned": dict(variant=variant, band=band)}),
         plain_fp64_ms_per_step=plain_ms,
         speedup_vs_plain_fp64=plain_ms / ms if plain_ms else None,
-        max_rel_err_vs_fp64=err)
+        max_rel_err_vs_fp64=err,
+        # whole macro steps (passes and combination) against the HBM peak
+        bandwidth=dict(method_bytes_per_step=step_bytes,
+                       achieved=step_bytes / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                       frac=step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       pass_kernel=kpass, pass_launches_per_step=pass_launches,
+                       traffic_bytes_per_step=traffic_bytes,
+                       traffic=traffic_bytes / (ms * 1e-3) / 1e9 if traffic_bytes else None,
+                       traffic_profile=tp["profile"] if tp and tc else None))
 
 
 def bench_batch(args):
@@ -320,7 +358,8 @@ def bench_batch(args):
     from synth import workloads
     if args.steps == 500:                 # the default: the batch workload's own length
         args.steps = workloads.CONFIG_BATCH["n_macro"]
-    leg = batch_leg(args.steps, args.warmup, args.dtype)
+    leg = batch_leg(args.steps, args.warmup, args.dtype,
+                    pin=(args.variant, args.band) if args.variant else None)
     rec = dict(
         metric="grid-pt RHS updates/s", value=leg["updates_per_s"], unit="grid-pt RHS updates/s",
         n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=leg["ms_per_step"],
@@ -328,7 +367,7 @@ def bench_batch(args):
         data="synthetic", config=leg["config"],
         plain_fp64_ms_per_step=leg["plain_fp64_ms_per_step"],
         speedup_vs_plain_fp64=leg["speedup_vs_plain_fp64"],
-        max_rel_err_vs_fp64=leg["max_rel_err_vs_fp64"],
+        max_rel_err_vs_fp64=leg["max_rel_err_vs_fp64"], bandwidth=leg["bandwidth"],
     )
     print(json.dumps(rec), flush=True)
 

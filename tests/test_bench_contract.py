@@ -49,6 +49,10 @@ def test_headline_json_line():
     assert bt["f64"]["speedup_vs_plain_fp64"] > 1.0 and bt["f64"]["steps"] == 100
     assert bt["f32"]["ms_per_step"] < bt["f64"]["ms_per_step"]
     assert bt["f32"]["max_rel_err_vs_fp64"] < 1e-4
+    for dt in ("f64", "f32"):
+        bw = bt[dt]["bandwidth"]
+        assert 0.0 < bw["frac"] < 1.0 and abs(bw["frac"] - bw["achieved"] / bw["peak"]) < 1e-9
+    assert bt["f32"]["bandwidth"]["method_bytes_per_step"] < bt["f64"]["bandwidth"]["method_bytes_per_step"]
     # the 3-D forward with 8 right-hand sides
     a3 = line["acoustic3d"]
     assert a3["config"]["grid"] == [384, 384, 384] and a3["config"]["n_rhs"] == 8
