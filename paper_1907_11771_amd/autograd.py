@@ -80,14 +80,17 @@ class _ReceiverTraces(torch.autograd.Function):
             fwd_lanes = plan.lanes
             if pairs is not None and plan.adjoint_lanes:
                 plan.set_lanes(plan.adjoint_lanes)
-            for m in range(e - 1, s - 1, -1):
-                if pairs is not None:
-                    plan.adjoint_step_pairs(t0 + m * plan.H, states[m - s], pairs[m - s], ybar,
-                                            trace_bar=gtr[m], grad_c2=grad)
-                else:
-                    plan.adjoint_step(t0 + m * plan.H, states[m - s], ybar, trace_bar=gtr[m],
-                                      grad_c2=grad)
-            plan.set_lanes(fwd_lanes)
+            try:
+                for m in range(e - 1, s - 1, -1):
+                    if pairs is not None:
+                        plan.adjoint_step_pairs(t0 + m * plan.H, states[m - s], pairs[m - s],
+                                                ybar, trace_bar=gtr[m], grad_c2=grad)
+                    else:
+                        plan.adjoint_step(t0 + m * plan.H, states[m - s], ybar,
+                                          trace_bar=gtr[m], grad_c2=grad)
+            finally:
+                # the forward's stream count, also when an adjoint step raises
+                plan.set_lanes(fwd_lanes)
         ctx.cps = None
         ctx.c2_fwd = None
         return ybar.to(ctx.y0_dtype), grad.to(ctx.c2_dtype), None, None, None, None, None
