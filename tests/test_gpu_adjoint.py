@@ -106,7 +106,7 @@ def test_checkpointed_misfit_gradient_matches_oracle(duplicate):
     loss = 0.5 * ((tr - to_dev(data)) ** 2).sum()
     loss.backward()
     L, gy, gc = AD.misfit_gradient(op, 0.0, y0, H, steps, c, n_macro, rec, data)
-    assert float(loss) == pytest.approx(L, rel=1e-12)
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-12)
     assert rel_err(y.grad.cpu().numpy()[0], gy, 0) <= 1e-11
     assert rel_err(c2.grad.cpu().numpy(), gc, None) <= 1e-11
 
