@@ -485,38 +485,60 @@ void adj_tile3d(const AdjArgs<T> a) {
         dv = -dd;
       }
       if (valid) {
+        // every load of the point is issued before its first store (the
+        // compiler cannot move a load across a store it may alias, and loads
+        // interleaved with stores would wait for one memory round trip each)
         const uint32_t idx = (uint32_t)z * plane + pil;
+        double g0 = 0.0;
+        if constexpr (GRAD) g0 = a.grad[idx];
         if constexpr (FIRST) {
+          T yb[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) yb[q] = a.ybar[base + q * (int64_t)F1 + idx];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int64_t fo = base + q * (int64_t)F1;
-            const T yb = a.ybar[fo + idx];
-            a.P[fo + idx] = ch * yb + h2 * (cq * at[q]);
-            a.Q[fo + idx] = ch * yb;
+            a.P[fo + idx] = ch * yb[q] + h2 * (cq * at[q]);
+            a.Q[fo + idx] = ch * yb[q];
           }
-          if constexpr (GRAD)
-            a.grad[idx] += 2.0 * a.h * ((double)cq * (double)a.ybar[base + idx]) * (double)dv;
+          if constexpr (GRAD) a.grad[idx] = g0 + 2.0 * a.h * ((double)cq * (double)yb[0]) * (double)dv;
         } else {
+          T qo[4], po[4];
+          double ya[4], fa[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) qo[q] = a.Q[base + q * (int64_t)F1 + idx];
+          if (a.last || GRAD) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (a.last || q == 0) po[q] = a.P[base + q * (int64_t)F1 + idx];
+          }
+          if (a.last && !a.first_seq) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              ya[q] = a.yacc[base + q * (int64_t)F1 + idx];
+              fa[q] = a.facc[base + q * (int64_t)F1 + idx];
+            }
+          }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int64_t fo = base + q * (int64_t)F1;
-            const T qn = a.Q[fo + idx] + h2 * at[q];
+            const T qn = qo[q] + h2 * at[q];
             if (!a.last) {
               a.Q[fo + idx] = qn;
             } else {
               const double l1 = (double)qn;
-              const double v0 = l1 + (double)a.P[fo + idx];
+              const double v0 = l1 + (double)po[q];
               const double f0 = a.h * l1;
               if (a.first_seq) {
                 a.yacc[fo + idx] = v0;
                 a.facc[fo + idx] = f0;
               } else {
-                a.yacc[fo + idx] += v0;
-                a.facc[fo + idx] += f0;
+                a.yacc[fo + idx] = ya[q] + v0;
+                a.facc[fo + idx] = fa[q] + f0;
               }
             }
           }
-          if constexpr (GRAD) a.grad[idx] += 2.0 * a.h * (double)a.P[base + idx] * (double)dv;
+          if constexpr (GRAD) a.grad[idx] = g0 + 2.0 * a.h * (double)po[0] * (double)dv;
         }
       }
 #pragma unroll

@@ -82,6 +82,52 @@ __device__ __forceinline__ T source_term(const SrcDesc* src, int nsrc, int64_t r
   return add;
 }
 
+// Store that does not keep the line in the caches (the level written now is
+// read again only one or two launches later, after the whole grid has
+// streamed through).
+template <bool NT, typename T>
+__device__ __forceinline__ void store(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// The leap-frog update y_{n+1} = y_{n-1} + 2h f of one point's F fields
+// (element offsets e0 + q * fstride) and, in a sequence's last step, the
+// average y* with c_j y* added to the FP64 accumulator (or, for the last
+// sequence, y_out formed).  `centre(q)` gives the point's value of y_n.
+// Every load is issued before the first store: the compiler cannot move a
+// load across a store it may alias, so loads interleaved with the stores
+// would each wait for a memory round trip.
+template <bool NT, int F, typename T, typename Centre>
+__device__ __forceinline__ void lf_point(const SeqDesc<T>& d, const StepArgs<T>& a, int64_t e0,
+                                         int64_t fstride, const T* f, Centre centre) {
+  T o[F];
+#pragma unroll
+  for (int q = 0; q < F; ++q) o[q] = d.old[e0 + q * fstride];
+  if (!(d.mode & MODE_LAST)) {
+#pragma unroll
+    for (int q = 0; q < F; ++q) store<NT>(d.out + e0 + q * fstride, o[q] + d.h2 * f[q]);
+    return;
+  }
+  T c[F];
+  double acc[F];
+#pragma unroll
+  for (int q = 0; q < F; ++q) {
+    c[q] = centre(q);
+    acc[q] = (d.mode & MODE_FIRST) ? 0.0 : a.acc[e0 + q * fstride];
+  }
+#pragma unroll
+  for (int q = 0; q < F; ++q) {
+    const int64_t e = e0 + q * fstride;
+    const T nw = o[q] + d.h2 * f[q];
+    const double ys = 0.25 * (((double)o[q] + 2.0 * (double)c[q]) + (double)nw);
+    double v = d.cw * ys;
+    if (!(d.mode & MODE_FIRST)) v = acc[q] + v;
+    if (d.mode & MODE_FINAL) store<NT>(a.yout + e, (T)v);
+    else store<NT>(a.acc + e, v);
+  }
+}
+
 template <typename T, int ORDER, int OP>
 __global__ __launch_bounds__(256) void lf_kernel(const StepArgs<T> a) {
   constexpr int F = NFields<OP>::F;
@@ -104,30 +150,8 @@ __global__ __launch_bounds__(256) void lf_kernel(const StepArgs<T> a) {
     eval_rhs<T, ORDER, OP>(d.cur + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
   }
   if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
-#pragma unroll
-  for (int q = 0; q < F; ++q) {
-    const int64_t e = base + q * a.g.field + idx;
-    const T o = d.old[e];
-    const T nw = o + d.h2 * f[q];
-    if (!(d.mode & MODE_LAST)) {
-      d.out[e] = nw;
-    } else {
-      const double ys = 0.25 * (((double)o + 2.0 * (double)d.cur[e]) + (double)nw);
-      double v = d.cw * ys;
-      if (!(d.mode & MODE_FIRST)) v = a.acc[e] + v;
-      if (d.mode & MODE_FINAL) a.yout[e] = (T)v;
-      else a.acc[e] = v;
-    }
-  }
-}
-
-// Store that does not keep the line in the caches (the level written now is
-// read again only one or two launches later, after the whole grid has
-// streamed through).
-template <bool NT, typename T>
-__device__ __forceinline__ void store(T* p, T v) {
-  if constexpr (NT) __builtin_nontemporal_store(v, p);
-  else *p = v;
+  const int64_t e0 = base + idx;
+  lf_point<false, F>(d, a, e0, a.g.field, f, [&](int q) { return d.cur[e0 + q * a.g.field]; });
 }
 
 // Workgroup index -> tile index so that each of the 8 XCDs (which receive
@@ -194,22 +218,8 @@ __global__ __launch_bounds__(256) void lf_march2d(const StepArgs<T> a) {
     f[2] = -(a.invy * syp);
     const int64_t idx = rowoff + x;
     if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int64_t e = base + q * F1 + idx;
-      const T o = d.old[e];
-      const T nw = o + d.h2 * f[q];
-      if (!(d.mode & MODE_LAST)) {
-        store<NT>(d.out + e, nw);
-      } else {
-        const T c = q == 0 ? pw[R] : (q == 1 ? cvx[idx] : vw[R]);
-        const double ys = 0.25 * (((double)o + 2.0 * (double)c) + (double)nw);
-        double v = d.cw * ys;
-        if (!(d.mode & MODE_FIRST)) v = a.acc[e] + v;
-        if (d.mode & MODE_FINAL) store<NT>(a.yout + e, (T)v);
-        else store<NT>(a.acc + e, v);
-      }
-    }
+    lf_point<NT, 3>(d, a, base + idx, F1, f,
+                    [&](int q) { return q == 0 ? pw[R] : (q == 1 ? cvx[idx] : vw[R]); });
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) {
       pw[k] = pw[k + 1];
@@ -291,22 +301,9 @@ __global__ __launch_bounds__(256) void lf_march3d(const StepArgs<T> a) {
     f[2] = -(a.invy * dsum<T, ORDER>(cp + col, y, ny, nx));
     f[3] = -(a.invz * szp);
     if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t e = base + q * F1 + idx;
-      const T o = d.old[e];
-      const T nw = o + d.h2 * f[q];
-      if (!(d.mode & MODE_LAST)) {
-        store<NT>(d.out + e, nw);
-      } else {
-        const T c = q == 0 ? pw[R] : (q == 3 ? vw[R] : (q == 1 ? cvx[idx] : cvy[idx]));
-        const double ys = 0.25 * (((double)o + 2.0 * (double)c) + (double)nw);
-        double v = d.cw * ys;
-        if (!(d.mode & MODE_FIRST)) v = a.acc[e] + v;
-        if (d.mode & MODE_FINAL) store<NT>(a.yout + e, (T)v);
-        else store<NT>(a.acc + e, v);
-      }
-    }
+    lf_point<NT, 4>(d, a, base + idx, F1, f, [&](int q) {
+      return q == 0 ? pw[R] : (q == 3 ? vw[R] : (q == 1 ? cvx[idx] : cvy[idx]));
+    });
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) {
       pw[k] = pw[k + 1];
@@ -464,6 +461,24 @@ __device__ __forceinline__ int tile3d_count(const Geometry& g, int tzn) {
   return ((g.nx + 63) / 64) * ((g.ny + 15) / 16) * ((g.nz + tzn - 1) / tzn);
 }
 
+// Whether a point source of right-hand side `rhs` lies in tile `tile` of
+// that blocking (its 64 x 16 columns and tzn planes, as tile3d_march lays
+// them out).  Found once per block, so that the sweeps search the sources
+// per point only in the few blocks that hold one.
+__device__ __forceinline__ bool tile3d_has_source(const SrcDesc* src, int nsrc, int64_t rhs,
+                                                  const Geometry& g, int tile, int tzn) {
+  const int ntx = (g.nx + 63) / 64, nty = (g.ny + 15) / 16;
+  const int x0 = (tile % ntx) * 64, y0 = ((tile / ntx) % nty) * 16;
+  const int z0 = (tile / (ntx * nty)) * tzn, z1 = min(z0 + tzn, g.nz);
+  for (int k = 0; k < nsrc; ++k) {
+    if (src[k].rhs != rhs) continue;
+    int x, y, z;
+    decompose(src[k].idx, g, x, y, z);
+    if (x >= x0 && x < x0 + 64 && y >= y0 && y < y0 + 16 && z >= z0 && z < z1) return true;
+  }
+  return false;
+}
+
 // Workgroup index -> (tile, sequence) for a launch of n sequences over
 // `tiles` tiles: the n workgroups of one tile are consecutive on one XCD
 // (they read the same c^2 tile, which then comes from that XCD's L2), and
@@ -490,27 +505,41 @@ void lf_tile3d(const StepArgs<T> a) {
   const int64_t rhs = blockIdx.z;
   const int64_t base = rhs * a.g.state;
   const int64_t F1 = a.g.field;
+  const bool srcs = a.g.nsrc && tile3d_has_source(a.src, a.g.nsrc, rhs, a.g, tile, tzn);
   tile3d_march<T, ORDER>(
       d.cur + base, a.g, a.invx, a.invy, a.invz, tile, tzn,
       [&](int64_t idx, T dvx, T dvy, T dvz, T* f, const T* c) {
-        const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
+        // every load of the point is issued before its first store: the
+        // compiler cannot move a load across a store it may alias, and loads
+        // interleaved with stores would wait for one memory round trip each
+        T c2 = a.c2c;
+        if (a.c2f) c2 = a.c2f[idx];
+        T o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = d.old[base + q * F1 + idx];
         f[0] = -(c2 * ((dvx + dvy) + dvz));
-        if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
+        if (srcs) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, d.amp);
+        if (!(d.mode & MODE_LAST)) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            // read back only by the next launch, after the whole grid
+            __builtin_nontemporal_store(o[q] + d.h2 * f[q], d.out + base + q * F1 + idx);
+          return;
+        }
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!(d.mode & MODE_FIRST)) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] = a.acc[base + q * F1 + idx];
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t e = base + q * F1 + idx;
-          const T o = d.old[e];
-          const T nw = o + d.h2 * f[q];
-          if (!(d.mode & MODE_LAST)) {
-            // read back only by the next launch, after the whole grid
-            __builtin_nontemporal_store(nw, d.out + e);
-          } else {
-            const double ys = 0.25 * (((double)o + 2.0 * (double)c[q]) + (double)nw);
-            double v = d.cw * ys;
-            if (!(d.mode & MODE_FIRST)) v = a.acc[e] + v;
-            if (d.mode & MODE_FINAL) a.yout[e] = (T)v;
-            else a.acc[e] = v;
-          }
+          const T nw = o[q] + d.h2 * f[q];
+          const double ys = 0.25 * (((double)o[q] + 2.0 * (double)c[q]) + (double)nw);
+          double v = d.cw * ys;
+          if (!(d.mode & MODE_FIRST)) v = acc[q] + v;
+          if (d.mode & MODE_FINAL) a.yout[e] = (T)v;
+          else a.acc[e] = v;
         }
       });
 }
@@ -523,13 +552,14 @@ void first_tile3d(const FirstArgs<T> a) {
   const int64_t rhs = blockIdx.z;
   const int64_t base = rhs * a.g.state;
   const int64_t F1 = a.g.field;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x), tzn = a.tz > 0 ? a.tz : TZ;
+  const bool srcs = a.g.nsrc && tile3d_has_source(a.src, a.g.nsrc, rhs, a.g, tile, tzn);
   tile3d_march<T, ORDER>(
-      a.y0 + base, a.g, a.invx, a.invy, a.invz, xcd_tile(blockIdx.x, gridDim.x),
-      a.tz > 0 ? a.tz : TZ,
+      a.y0 + base, a.g, a.invx, a.invy, a.invz, tile, tzn,
       [&](int64_t idx, T dvx, T dvy, T dvz, T* f, const T* c) {
         const T c2 = a.c2f ? a.c2f[idx] : a.c2c;
         f[0] = -(c2 * ((dvx + dvy) + dvz));
-        if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
+        if (srcs) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t fo = base + q * F1;
