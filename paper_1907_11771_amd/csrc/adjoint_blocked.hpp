@@ -253,6 +253,11 @@ void adj_pass2d(const AdjPassArgs<T> a) {
           const int64_t pt = (int64_t)level_row() * nx + gx;
           const bool store = lane_ok && yo >= ya && yo < yb;
           if (store) {
+            // the gradient row sum is read before the level stores: the
+            // compiler cannot move the load across stores it may alias, and
+            // behind them its wait would also wait for every store
+            double* gp = d.gsum + (int64_t)blockIdx.z * F1 + pt;
+            const double gold = first ? 0.0 : *gp;
             if (!final_) {
 #pragma unroll
               for (int q = 0; q < 3; ++q) {
@@ -273,10 +278,8 @@ void adj_pass2d(const AdjPassArgs<T> a) {
                 d.f1[base + pt + q * F1] = (double)h * l1[q];
               }
             }
-            double* gp = d.gsum + (int64_t)blockIdx.z * F1 + pt;
             const double add = myg[sl * 64] / (double)c2;
-            if (first) *gp = add;
-            else *gp += add;
+            *gp = first ? add : gold + add;
           }
           myg[sl * 64] = 0.0;
         } else if (e < G) {

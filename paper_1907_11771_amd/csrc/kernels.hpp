@@ -712,18 +712,28 @@ __global__ __launch_bounds__(256) void rk4_stage(const RK4Args<T> a) {
     eval_rhs<T, ORDER, OP>(a.ys + base, x, y, z, a.g, c2, a.invx, a.invy, a.invz, f);
   }
   if (a.g.nsrc) f[0] += source_term<T>(a.src, a.g.nsrc, rhs, idx, a.amp);
+  // every load of the point before its first store (the compiler cannot move
+  // a load across a store it may alias)
+  T yn[F];
+  double acc[F];
+#pragma unroll
+  for (int q = 0; q < F; ++q) {
+    const int64_t e = base + q * a.g.field + idx;
+    yn[q] = a.yn[e];
+    acc[q] = a.stage == 0 ? 0.0 : a.acc[e];
+  }
 #pragma unroll
   for (int q = 0; q < F; ++q) {
     const int64_t e = base + q * a.g.field + idx;
     const double k = (double)f[q];
     if (a.stage == 0) {
       a.acc[e] = k;
-      a.out[e] = a.yn[e] + (T)(0.5 * a.h) * f[q];
+      a.out[e] = yn[q] + (T)(0.5 * a.h) * f[q];
     } else if (a.stage < 3) {
-      a.acc[e] = a.acc[e] + 2.0 * k;
-      a.out[e] = a.yn[e] + (T)(a.stage == 1 ? 0.5 * a.h : a.h) * f[q];
+      a.acc[e] = acc[q] + 2.0 * k;
+      a.out[e] = yn[q] + (T)(a.stage == 1 ? 0.5 * a.h : a.h) * f[q];
     } else {
-      a.out[e] = (T)((double)a.yn[e] + (a.h / 6.0) * (a.acc[e] + k));
+      a.out[e] = (T)((double)yn[q] + (a.h / 6.0) * (acc[q] + k));
     }
   }
 }
