@@ -116,16 +116,20 @@ __global__ __launch_bounds__(256) void adj_first_kernel(const AdjArgs<T> a) {
     eval_AT<T, ORDER, OP>(a.ybar + base, a.c2f, a.c2c, x, y, z, a.g, a.invx, a.invy, a.invz, at);
     const T cq = (T)(0.25 * a.cw), ch = (T)(0.5 * a.cw);
     const T h2 = (T)(2.0 * a.h);
+    // every load before the first store (the compiler cannot move a load
+    // across a store it may alias)
+    T yb[F];
+#pragma unroll
+    for (int q = 0; q < F; ++q) yb[q] = a.ybar[base + q * a.g.field + idx];
+    if (a.grad) {
+      const T dv = neg_div<T, ORDER, OP>(a.level + base, x, y, z, a.g, a.invx, a.invy, a.invz);
+      gsum += 2.0 * a.h * ((double)cq * (double)yb[0]) * (double)dv;
+    }
 #pragma unroll
     for (int q = 0; q < F; ++q) {
       const int64_t e = base + q * a.g.field + idx;
-      const T yb = a.ybar[e];
-      a.P[e] = ch * yb + h2 * (cq * at[q]);           // lambda_N
-      a.Q[e] = ch * yb;                               // lambda_{N-1} so far
-    }
-    if (a.grad) {
-      const T dv = neg_div<T, ORDER, OP>(a.level + base, x, y, z, a.g, a.invx, a.invy, a.invz);
-      gsum += 2.0 * a.h * ((double)cq * (double)a.ybar[base + idx]) * (double)dv;
+      a.P[e] = ch * yb[q] + h2 * (cq * at[q]);        // lambda_N
+      a.Q[e] = ch * yb[q];                            // lambda_{N-1} so far
     }
   }
   if (a.grad) a.grad[idx] += gsum;
@@ -146,29 +150,41 @@ __global__ __launch_bounds__(256) void adj_lf_kernel(const AdjArgs<T> a) {
     const int64_t base = (int64_t)r * a.g.state;
     T at[F];
     eval_AT<T, ORDER, OP>(a.P + base, a.c2f, a.c2c, x, y, z, a.g, a.invx, a.invy, a.invz, at);
+    // every load before the first store (the compiler cannot move a load
+    // across a store it may alias)
+    T qo[F], po[F];
+    double ya[F], fa[F];
 #pragma unroll
     for (int q = 0; q < F; ++q) {
       const int64_t e = base + q * a.g.field + idx;
-      const T qn = a.Q[e] + h2 * at[q];
+      qo[q] = a.Q[e];
+      po[q] = (a.last || (a.grad && q == 0)) ? a.P[e] : T(0);
+      ya[q] = (a.last && !a.first_seq) ? a.yacc[e] : 0.0;
+      fa[q] = (a.last && !a.first_seq) ? a.facc[e] : 0.0;
+    }
+    if (a.grad) {
+      const T dv = neg_div<T, ORDER, OP>(a.level + base, x, y, z, a.g, a.invx, a.invy, a.invz);
+      gsum += 2.0 * a.h * (double)po[0] * (double)dv;
+    }
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+      const int64_t e = base + q * a.g.field + idx;
+      const T qn = qo[q] + h2 * at[q];
       if (!a.last) {
         a.Q[e] = qn;
       } else {
         // here qn = lambda_1 (final) and P = lambda_2 = lambda_0 (its only term)
         const double l1 = (double)qn;
-        const double v0 = l1 + (double)a.P[e];       // lambda_0 + lambda_1
+        const double v0 = l1 + (double)po[q];        // lambda_0 + lambda_1
         const double f0 = a.h * l1;                  // h_j lambda_1
         if (a.first_seq) {
           a.yacc[e] = v0;
           a.facc[e] = f0;
         } else {
-          a.yacc[e] += v0;
-          a.facc[e] += f0;
+          a.yacc[e] = ya[q] + v0;
+          a.facc[e] = fa[q] + f0;
         }
       }
-    }
-    if (a.grad) {
-      const T dv = neg_div<T, ORDER, OP>(a.level + base, x, y, z, a.g, a.invx, a.invy, a.invz);
-      gsum += 2.0 * a.h * (double)a.P[base + idx] * (double)dv;
     }
   }
   if (a.grad) a.grad[idx] += gsum;
@@ -272,37 +288,51 @@ void adj_march3d(const AdjArgs<T> a) {
         dd += a.invz * sl;
         dv = -dd;
       }
+      // every load of the point before its first store (the compiler cannot
+      // move a load across a store it may alias)
+      const double g0 = wantg ? a.grad[idx] : 0.0;
       if constexpr (FIRST) {
+        T yb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) yb[q] = a.ybar[base + q * F1 + idx];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t fo = base + q * F1;
-          const T yb = a.ybar[fo + idx];
-          a.P[fo + idx] = ch * yb + h2 * (cq * at[q]);
-          a.Q[fo + idx] = ch * yb;
+          a.P[fo + idx] = ch * yb[q] + h2 * (cq * at[q]);
+          a.Q[fo + idx] = ch * yb[q];
         }
-        if (wantg)
-          a.grad[idx] += 2.0 * a.h * ((double)cq * (double)a.ybar[base + idx]) * (double)dv;
+        if (wantg) a.grad[idx] = g0 + 2.0 * a.h * ((double)cq * (double)yb[0]) * (double)dv;
       } else {
+        T qo[4], po[4];
+        double ya[4], fa[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t fo = base + q * F1;
-          const T qn = a.Q[fo + idx] + h2 * at[q];
+          qo[q] = a.Q[fo + idx];
+          po[q] = (a.last || (wantg && q == 0)) ? a.P[fo + idx] : T(0);
+          ya[q] = (a.last && !a.first_seq) ? a.yacc[fo + idx] : 0.0;
+          fa[q] = (a.last && !a.first_seq) ? a.facc[fo + idx] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t fo = base + q * F1;
+          const T qn = qo[q] + h2 * at[q];
           if (!a.last) {
             a.Q[fo + idx] = qn;
           } else {
             const double l1 = (double)qn;
-            const double v0 = l1 + (double)a.P[fo + idx];
+            const double v0 = l1 + (double)po[q];
             const double f0 = a.h * l1;
             if (a.first_seq) {
               a.yacc[fo + idx] = v0;
               a.facc[fo + idx] = f0;
             } else {
-              a.yacc[fo + idx] += v0;
-              a.facc[fo + idx] += f0;
+              a.yacc[fo + idx] = ya[q] + v0;
+              a.facc[fo + idx] = fa[q] + f0;
             }
           }
         }
-        if (wantg) a.grad[idx] += 2.0 * a.h * (double)a.P[base + idx] * (double)dv;
+        if (wantg) a.grad[idx] = g0 + 2.0 * a.h * (double)po[0] * (double)dv;
       }
 #pragma unroll
       for (int k = 0; k < 2 * R; ++k) {
@@ -609,16 +639,18 @@ __global__ __launch_bounds__(256) void adj_final_kernel(const AdjFinalArgs<T> a)
       at[0] += a.invz * dsum<double, ORDER>(fp + 3 * a.g.field + zline, z, a.g.nz, plane);
       at[3] = a.invz * sz;
     }
+    // every load before the first store (the compiler cannot move a load
+    // across a store it may alias)
+    double ya[F];
 #pragma unroll
-    for (int q = 0; q < F; ++q) {
-      const int64_t e = base + q * a.g.field + idx;
-      a.ybar[e] = (T)(a.yacc[e] + at[q]);
-    }
+    for (int q = 0; q < F; ++q) ya[q] = a.yacc[base + q * a.g.field + idx];
     if (a.grad) {
       const T dv = neg_div<T, ORDER, OP>(a.y0 + base, x, y, z, a.g, (T)a.invx, (T)a.invy,
                                          (T)a.invz);
       gsum += fp[idx] * (double)dv;
     }
+#pragma unroll
+    for (int q = 0; q < F; ++q) a.ybar[base + q * a.g.field + idx] = (T)(ya[q] + at[q]);
   }
   if (a.grad) a.grad[idx] += gsum;
 }
