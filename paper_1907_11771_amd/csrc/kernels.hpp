@@ -451,10 +451,13 @@ __device__ __forceinline__ void tile3d_march(const T* __restrict__ cp, const Geo
   }
 }
 
-// Two blocks per CU (8 waves per SIMD) need at most 64 VGPRs: asked for in
-// FP32, where the sweep fits them; FP64 runs one block per CU.
+// One 1024-thread block per CU (4 waves per SIMD, up to 128 VGPRs) in both
+// precisions.  Two blocks per CU would need the FP32 sweep in 64 VGPRs, where
+// it spills, and each reload from the spill area waits for the plane's
+// prefetched loads as well; with a point's loads issued ahead of its stores
+// one block keeps enough memory operations in flight.
 template <typename T>
-constexpr int tile3d_waves() { return sizeof(T) == 4 ? 8 : 4; }
+constexpr int tile3d_waves() { return 4; }
 
 // Tiles of the 64 x 16 x tzn blocking of lf_tile3d / first_tile3d.
 __device__ __forceinline__ int tile3d_count(const Geometry& g, int tzn) {
